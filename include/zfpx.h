@@ -1,0 +1,249 @@
+/*
+ * zfpx.h -- fixed-rate ZFP coding of spectral-transform transpose buffers on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The paper this implements (Breschi & Vella, "Toward GPU-Resident Climate
+ * Models: a feasibility study on lossy compression for the spherical harmonic
+ * transform's communication bottleneck") compresses, on the GPU, each
+ * outgoing buffer of the spectral transform's pencil transpositions just
+ * before the all-to-all and decompresses it on the receiver before any
+ * computation, with no host-device copies (Section I).  It uses ZFP in
+ * fixed-rate mode: 4x4x4 blocks coded independently into exactly r bits per
+ * value, so every message has a size known in advance (Sections II-C and
+ * III-B), and compares with casting the buffer to float16 and back (Sections I
+ * and III-F).
+ *
+ * Conventions common to every entry point
+ *  - Device buffers are caller-owned device memory (hipMalloc or a PyTorch
+ *    tensor); the library never frees them.  Host arrays are read during the
+ *    call only.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Hot-path calls
+ *    only validate their arguments on the host and enqueue kernels: they
+ *    allocate nothing, copy nothing between host and device and never
+ *    synchronise, so they may be captured into a HIP graph.
+ *  - Return value: ZFPX_OK (0) or a negative zfpx_status.  On an argument
+ *    error nothing is enqueued.  A fault inside an enqueued kernel surfaces
+ *    at the caller's next synchronisation, as with any HIP kernel.
+ *  - Rates are integers 1..32 (bits per value); a block takes 64*rate bits =
+ *    `rate` 64-bit words.
+ *  - Arrays are float32 with x the fastest axis.  A 3-D array of nx*ny*nz
+ *    values has ceil(nx/4)*ceil(ny/4)*ceil(nz/4) blocks, numbered with the x
+ *    block fastest, then y, then z; partial blocks are completed by repeating
+ *    the last value along each axis (clamp to edge), and decoding writes only
+ *    positions inside the array.
+ *  - Non-finite inputs (inf, NaN) are outside the contract: the output is
+ *    deterministic but unspecified.
+ */
+#ifndef ZFPX_H
+#define ZFPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum zfpx_status {
+  ZFPX_OK = 0,
+  ZFPX_EINVAL = -1, /* bad argument: rate, size, null or misaligned pointer */
+  ZFPX_ENOSPC = -2, /* output buffer smaller than the coded size */
+  ZFPX_EHIP = -3,   /* a HIP runtime call failed */
+  ZFPX_ENOMEM = -4, /* a library allocation failed (plans, graphs, servers) */
+  ZFPX_EAGAIN = -5, /* the serving queue is full; try again */
+  ZFPX_ESTATE = -6  /* object used in the wrong state */
+};
+
+/* Human-readable name of a status code (static string). */
+const char* zfpx_status_string(int status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int zfpx_version(void);
+
+/* Number of compute units of the current device (0 if unknown). */
+int zfpx_device_cus(void);
+
+/* -------------------------------------------------------------------------
+ * Regular 3-D arrays
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Coded size in bytes of an nx*ny*nz array at `rate` bits per value:
+ * ceil(nx/4)*ceil(ny/4)*ceil(nz/4) * 8 * rate (fixed-rate mode gives every
+ * block exactly 64*rate bits; paper Section II-C and Table 1).  Returns a
+ * negative zfpx_status for a bad rate or negative sizes.
+ */
+int64_t zfpx_fixed_rate_bytes(int64_t nx, int64_t ny, int64_t nz, int rate);
+
+/*
+ * Encode a strided float32 array (element (x,y,z) at d_in[x*sx + y*sy + z*sz])
+ * into `rate` words per block at d_out, blocks in order (paper Section II-C:
+ * independent 4^3 blocks, lifting transform, precision reduction, exactly
+ * `rate` bits per value).
+ *   d_out     : device, 8-byte aligned, at least zfpx_fixed_rate_bytes(...)
+ *               bytes (out_bytes); ZFPX_ENOSPC if smaller.
+ *   nx,ny,nz  : >= 0; an empty array enqueues nothing.
+ * The caller guarantees that every element offset is inside d_in.
+ */
+int zfpx_encode_fixed_rate(const float* d_in, int64_t nx, int64_t ny, int64_t nz, int64_t sx,
+                           int64_t sy, int64_t sz, int rate, void* d_out, size_t out_bytes,
+                           void* stream);
+
+/*
+ * Decode a stream made by zfpx_encode_fixed_rate (same dims and rate) into
+ * d_out[x*sx + y*sy + z*sz]; only positions inside the array are written.
+ *   d_in      : device, 8-byte aligned, in_bytes >= the coded size (ENOSPC).
+ * Any bit pattern decodes without a fault (every block reads only its own
+ * `rate` words).
+ */
+int zfpx_decode_fixed_rate(const void* d_in, size_t in_bytes, int64_t nx, int64_t ny,
+                           int64_t nz, int64_t sx, int64_t sy, int64_t sz, int rate,
+                           float* d_out, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Transpose-buffer plans: per-destination chunks with ragged rows
+ * ---------------------------------------------------------------------- */
+
+/*
+ * A plan describes how one GPU's transpose buffer is cut into per-destination
+ * chunks (paper Section II-B: every rank sends a sub-array to every other rank
+ * of its row or column; Table 1: each message is coded as its own array).
+ *
+ * Chunk c (0 <= c < nchunks) is a 3-D view of a float32 buffer:
+ *   levels z = 0..levels[c]-1 at element offset chunk_base[c] + z*level_stride[c];
+ *   rows r = row_start[c]..row_start[c+1]-1 at further offset row_offset[r],
+ *   each of row_len[r] >= 1 contiguous points.
+ * Rows are taken in groups of four in order; a group is as wide as its
+ * longest row; shorter rows and missing rows/levels are padded by clamping to
+ * the last point/row/level.  Chunk c has ceil(levels/4) * sum over groups of
+ * ceil(width/4) blocks, numbered (level block, group, x block) with the x block
+ * fastest, and its stream starts at byte 8*rate*(blocks of chunks < c): the
+ * send buffer is the concatenation of the chunk streams, ready for an
+ * all-to-all(v) whose counts follow from geometry alone.
+ *
+ * All arrays are host arrays; row_start has nchunks+1 entries starting at 0.
+ * zfpx_plan_create copies them into device tables (it allocates device
+ * memory and synchronises; call it outside hot loops).  Plans are immutable
+ * and may be used concurrently on several streams.  Errors: EINVAL for
+ * inconsistent tables or more than 2^31-1 blocks, ENOMEM/EHIP on allocation.
+ */
+typedef struct zfpx_plan zfpx_plan;
+
+int zfpx_plan_create(int32_t nchunks, const int64_t* chunk_base, const int64_t* level_stride,
+                     const int32_t* levels, const int32_t* row_start, const int64_t* row_offset,
+                     const int32_t* row_len, zfpx_plan** out);
+int zfpx_plan_destroy(zfpx_plan* plan);
+
+/*
+ * Plan facts: total blocks, real (unpadded) values, and the smallest buffer
+ * size in elements that holds every chunk point (any pointer may be NULL).
+ */
+int zfpx_plan_info(const zfpx_plan* plan, int64_t* nblocks, int64_t* nvalues,
+                   int64_t* min_buffer_elems);
+
+/*
+ * Coded sizes at `rate`: per chunk bytes and byte offsets (host arrays of
+ * nchunks entries, or NULL) and the total.
+ */
+int zfpx_plan_sizes(const zfpx_plan* plan, int rate, int64_t* chunk_bytes,
+                    int64_t* chunk_offsets, int64_t* total_bytes);
+
+/*
+ * Fused pack + encode of every chunk of `plan` read from d_src (src_elems
+ * float32 elements; EINVAL if a chunk point lies beyond) into d_send
+ * (8-byte aligned; ENOSPC if send_bytes is below the plan's total).  One
+ * launch covers all chunks (paper Section I: compress the outgoing buffer
+ * on the GPU immediately before the all-to-all).
+ */
+int zfpx_pack_encode(const zfpx_plan* plan, const float* d_src, int64_t src_elems, int rate,
+                     void* d_send, size_t send_bytes, void* stream);
+
+/*
+ * Fused decode + unpack: the mirror of zfpx_pack_encode; writes only the
+ * chunk points of d_dst (dst_elems elements).  (Paper Section I: decompress on
+ * the receiving side before any local computation.)
+ */
+int zfpx_decode_unpack(const zfpx_plan* plan, const void* d_recv, size_t recv_bytes, int rate,
+                       float* d_dst, int64_t dst_elems, void* stream);
+
+/*
+ * The same two operations restricted to chunks [first, first+count); the
+ * streams are read/written at their offsets inside the whole send buffer, so
+ * d_send/d_recv still point at the start of the buffer.  This is the
+ * one-launch-per-chunk form, and the unit for overlapping coding with
+ * sending chunk by chunk (paper Section III-D: the serial model could be
+ * pipelined).
+ */
+int zfpx_pack_encode_chunks(const zfpx_plan* plan, int32_t first, int32_t count,
+                            const float* d_src, int64_t src_elems, int rate, void* d_send,
+                            size_t send_bytes, void* stream);
+int zfpx_decode_unpack_chunks(const zfpx_plan* plan, int32_t first, int32_t count,
+                              const void* d_recv, size_t recv_bytes, int rate, float* d_dst,
+                              int64_t dst_elems, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Launch configuration and autotuning
+ * ---------------------------------------------------------------------- */
+
+/*
+ * A launch configuration: workgroup size in threads (64, 128 or 256; one
+ * 64-block tile per wavefront) and the grid in workgroups (0 = one tile per
+ * wavefront, i.e. as many workgroups as needed; otherwise a persistent grid
+ * that loops over tiles).  op: 0 = pack_encode, 1 = decode_unpack.
+ * zfpx_plan_set_config stores it in the plan for that op and rate (rate 0 =
+ * every rate without an entry of its own); it is then used by every launch
+ * on that plan.  Returns EINVAL for an unsupported configuration.
+ */
+int zfpx_plan_set_config(zfpx_plan* plan, int op, int rate, int wg_threads, int grid_wgs);
+int zfpx_plan_get_config(const zfpx_plan* plan, int op, int rate, int* wg_threads,
+                         int* grid_wgs);
+
+/*
+ * Autotune: time every candidate configuration for `op` and `rate` on this
+ * plan with the given buffers (the op is run repeatedly; outputs are
+ * overwritten), keep the fastest in the plan and, when cache_path is not
+ * NULL, record it in a small text cache keyed by device, op, rate and plan
+ * shape (read first: a cached entry skips the timing).  Synchronises the
+ * stream; not for hot loops.  best_us receives the chosen mean time.
+ */
+int zfpx_autotune(zfpx_plan* plan, int op, int rate, const float* d_src, int64_t src_elems,
+                  void* d_stream_buf, size_t stream_bytes, float* d_dst, int64_t dst_elems,
+                  const char* cache_path, void* stream, double* best_us);
+
+/* -------------------------------------------------------------------------
+ * Batched form captured in a HIP graph
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Capture, on a private stream, one pack_encode launch over every chunk of
+ * the plan (d_src -> d_send) followed by one decode_unpack launch
+ * (d_send -> d_dst), and instantiate the graph.  Each zfpx_graph_launch is
+ * then a single hipGraphLaunch on `stream`.  Buffers are bound at creation.
+ */
+typedef struct zfpx_graph zfpx_graph;
+
+int zfpx_graph_create(const zfpx_plan* plan, int rate, const float* d_src, int64_t src_elems,
+                      void* d_send, size_t send_bytes, float* d_dst, int64_t dst_elems,
+                      zfpx_graph** out);
+int zfpx_graph_launch(zfpx_graph* graph, void* stream);
+int zfpx_graph_destroy(zfpx_graph* graph);
+
+/* -------------------------------------------------------------------------
+ * float16 comparator
+ * ---------------------------------------------------------------------- */
+
+/*
+ * f16_truncate: d_out[i] = IEEE binary16 of d_in[i], rounded to nearest with
+ * ties to even (subnormals kept, overflow to infinity, NaN stays NaN).
+ * f16_restore: exact widening back to float32.  The paper's comparator casts
+ * the buffer to float16 before sending and back on receipt (Sections I and
+ * III-F).  n may be 0; pointers must be 4-byte (in) / 2-byte (out) aligned.
+ */
+int f16_truncate(const float* d_in, size_t n, uint16_t* d_out, void* stream);
+int f16_restore(const uint16_t* d_in, size_t n, float* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZFPX_H */

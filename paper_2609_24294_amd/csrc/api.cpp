@@ -1,0 +1,565 @@
+// api.cpp -- the C ABI: argument checks, plan construction, launch
+// configuration, autotuning and HIP-graph capture.  Hot-path entry points only
+// check arguments on the host and enqueue kernels.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/zfpx.h"
+#include "internal.hpp"
+
+using namespace zfpx;
+
+namespace {
+
+constexpr int64_t kMaxBlocks = 0x7fffffffLL;
+
+bool rate_ok(int rate) { return rate >= 1 && rate <= 32; }
+int64_t ceil4(int64_t n) { return (n + 3) / 4; }
+bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+LaunchCfg default_cfg(int rate) {
+  LaunchCfg c;
+  c.wg = 256;
+  c.grid = 0;
+  while (c.wg > 64 && lds_bytes(c.wg, rate) > device_max_lds()) c.wg /= 2;
+  return c;
+}
+
+bool cfg_ok(LaunchCfg c, int rate) {
+  if (c.wg != 64 && c.wg != 128 && c.wg != 256) return false;
+  if (c.grid < 0) return false;
+  return lds_bytes(c.wg, rate) <= device_max_lds();
+}
+
+}  // namespace
+
+struct zfpx_plan {
+  int32_t nchunks = 0;
+  int64_t nblocks = 0, nvalues = 0, min_elems = 0;
+  bool vec4 = true;
+  std::vector<int64_t> chunk_blocks, chunk_first;  // host copies
+  std::vector<int64_t> shape_key;                   // for the tuning cache
+  SegDesc* d_segs = nullptr;
+  int32_t* d_seg_block0 = nullptr;
+  int32_t* d_tile_seg = nullptr;
+  PlanDev dev{};
+  std::map<std::pair<int, int>, LaunchCfg> cfg;  // (op, rate) -> config; rate 0 = any
+
+  LaunchCfg config(int op, int rate) const {
+    auto it = cfg.find({op, rate});
+    if (it != cfg.end()) return it->second;
+    it = cfg.find({op, 0});
+    if (it != cfg.end() && lds_bytes(it->second.wg, rate) <= device_max_lds()) return it->second;
+    return default_cfg(rate);
+  }
+};
+
+struct zfpx_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+const char* zfpx_status_string(int status) {
+  switch (status) {
+    case ZFPX_OK: return "ok";
+    case ZFPX_EINVAL: return "invalid argument";
+    case ZFPX_ENOSPC: return "output buffer too small";
+    case ZFPX_EHIP: return "HIP runtime error";
+    case ZFPX_ENOMEM: return "out of memory";
+    case ZFPX_EAGAIN: return "queue full, try again";
+    case ZFPX_ESTATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+int zfpx_version(void) { return 100; }
+
+int zfpx_device_cus(void) { return device_cu_count(); }
+
+int64_t zfpx_fixed_rate_bytes(int64_t nx, int64_t ny, int64_t nz, int rate) {
+  if (!rate_ok(rate) || nx < 0 || ny < 0 || nz < 0) return ZFPX_EINVAL;
+  int64_t nb = ceil4(nx) * ceil4(ny) * ceil4(nz);
+  return nb * 8 * rate;
+}
+
+// ---------------------------------------------------------------------------
+// Regular arrays
+// ---------------------------------------------------------------------------
+
+static int regular_setup(int64_t nx, int64_t ny, int64_t nz, int64_t sx, int64_t sy, int64_t sz,
+                         int rate, RegularDev* g, int64_t* nblocks) {
+  if (!rate_ok(rate) || nx < 0 || ny < 0 || nz < 0) return ZFPX_EINVAL;
+  int64_t nbx = ceil4(nx), nby = ceil4(ny), nbz = ceil4(nz);
+  int64_t nb = nbx * nby * nbz;
+  if (nb > kMaxBlocks) return ZFPX_EINVAL;
+  *g = RegularDev{nx, ny, nz, sx, sy, sz, (int32_t)nbx, (int32_t)nby};
+  *nblocks = nb;
+  return ZFPX_OK;
+}
+
+static bool regular_vec4(const void* p, int64_t sx, int64_t sy, int64_t sz) {
+  return sx == 1 && (sy & 3) == 0 && (sz & 3) == 0 && aligned(p, 16);
+}
+
+int zfpx_encode_fixed_rate(const float* d_in, int64_t nx, int64_t ny, int64_t nz, int64_t sx,
+                           int64_t sy, int64_t sz, int rate, void* d_out, size_t out_bytes,
+                           void* stream) {
+  RegularDev g;
+  int64_t nb;
+  int st = regular_setup(nx, ny, nz, sx, sy, sz, rate, &g, &nb);
+  if (st) return st;
+  if (nb == 0) return ZFPX_OK;
+  if (!d_in || !d_out || !aligned(d_out, 8)) return ZFPX_EINVAL;
+  if ((int64_t)out_bytes < nb * 8 * rate) return ZFPX_ENOSPC;
+  hipError_t e = launch_regular_encode(g, regular_vec4(d_in, sx, sy, sz), d_in, (uint64_t*)d_out,
+                                       rate, (int32_t)nb, default_cfg(rate), (hipStream_t)stream);
+  return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
+}
+
+int zfpx_decode_fixed_rate(const void* d_in, size_t in_bytes, int64_t nx, int64_t ny, int64_t nz,
+                           int64_t sx, int64_t sy, int64_t sz, int rate, float* d_out,
+                           void* stream) {
+  RegularDev g;
+  int64_t nb;
+  int st = regular_setup(nx, ny, nz, sx, sy, sz, rate, &g, &nb);
+  if (st) return st;
+  if (nb == 0) return ZFPX_OK;
+  if (!d_in || !d_out || !aligned(d_in, 8)) return ZFPX_EINVAL;
+  if ((int64_t)in_bytes < nb * 8 * rate) return ZFPX_ENOSPC;
+  hipError_t e = launch_regular_decode(g, regular_vec4(d_out, sx, sy, sz), (const uint64_t*)d_in,
+                                       d_out, rate, (int32_t)nb, default_cfg(rate),
+                                       (hipStream_t)stream);
+  return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+
+int zfpx_plan_destroy(zfpx_plan* p) {
+  if (!p) return ZFPX_EINVAL;
+  if (p->d_segs) (void)hipFree(p->d_segs);
+  if (p->d_seg_block0) (void)hipFree(p->d_seg_block0);
+  if (p->d_tile_seg) (void)hipFree(p->d_tile_seg);
+  delete p;
+  return ZFPX_OK;
+}
+
+int zfpx_plan_create(int32_t nchunks, const int64_t* chunk_base, const int64_t* level_stride,
+                     const int32_t* levels, const int32_t* row_start, const int64_t* row_offset,
+                     const int32_t* row_len, zfpx_plan** out) {
+  if (!out || nchunks < 0) return ZFPX_EINVAL;
+  *out = nullptr;
+  if (nchunks > 0 && (!chunk_base || !level_stride || !levels || !row_start)) return ZFPX_EINVAL;
+  if (nchunks > 0 && row_start[0] != 0) return ZFPX_EINVAL;
+  for (int c = 0; c < nchunks; c++) {
+    if (row_start[c + 1] < row_start[c] || levels[c] < 0 || level_stride[c] < 0 ||
+        chunk_base[c] < 0)
+      return ZFPX_EINVAL;
+  }
+  int64_t nrows_total = nchunks > 0 ? row_start[nchunks] : 0;
+  if (nrows_total > 0 && (!row_offset || !row_len)) return ZFPX_EINVAL;
+  for (int64_t r = 0; r < nrows_total; r++)
+    if (row_len[r] < 1 || row_offset[r] < 0) return ZFPX_EINVAL;
+
+  zfpx_plan* p = new (std::nothrow) zfpx_plan();
+  if (!p) return ZFPX_ENOMEM;
+  p->nchunks = nchunks;
+  p->chunk_blocks.assign(nchunks, 0);
+  p->chunk_first.assign(nchunks + 1, 0);
+  std::vector<SegDesc> segs;
+  std::vector<int32_t> seg_block0;
+  int64_t total = 0, values = 0, min_elems = 0;
+  bool vec4 = true;
+  for (int c = 0; c < nchunks; c++) {
+    int64_t r0 = row_start[c], nrows = row_start[c + 1] - r0, L = levels[c];
+    int64_t ngroups = ceil4(nrows);
+    std::vector<int64_t> width(ngroups, 0);
+    for (int64_t g = 0; g < ngroups; g++)
+      for (int64_t r = 4 * g; r < std::min(4 * g + 4, nrows); r++)
+        width[g] = std::max<int64_t>(width[g], row_len[r0 + r]);
+    int64_t per_lb = 0;
+    for (int64_t g = 0; g < ngroups; g++) per_lb += ceil4(width[g]);
+    int64_t cb = (L > 0 && nrows > 0) ? ceil4(L) * per_lb : 0;
+    p->chunk_first[c] = total;
+    p->chunk_blocks[c] = cb;
+    if (cb > 0) {
+      if ((level_stride[c] & 3) != 0 || (chunk_base[c] & 3) != 0) vec4 = false;
+      for (int64_t r = r0; r < r0 + nrows; r++) {
+        if ((row_offset[r] & 3) != 0) vec4 = false;
+        values += L * row_len[r];
+        min_elems = std::max(min_elems, chunk_base[c] + (L - 1) * level_stride[c] + row_offset[r] +
+                                            row_len[r]);
+      }
+      for (int64_t bz = 0; bz < ceil4(L); bz++) {
+        for (int64_t g = 0; g < ngroups; g++) {
+          SegDesc d{};
+          for (int dy = 0; dy < 4; dy++) {
+            int64_t r = r0 + std::min<int64_t>(4 * g + dy, nrows - 1);
+            d.rbase[dy] = chunk_base[c] + 4 * bz * level_stride[c] + row_offset[r];
+            d.rlen[dy] = row_len[r];
+          }
+          d.lstride = level_stride[c];
+          d.block0 = (int32_t)(total + bz * per_lb);  // fixed below if it overflows
+          d.nbx = (int32_t)ceil4(width[g]);
+          d.nlev = (int32_t)std::min<int64_t>(4, L - 4 * bz);
+          d.nrow = (int32_t)std::min<int64_t>(4, nrows - 4 * g);
+          segs.push_back(d);
+        }
+      }
+      // block0 of each run: running sum in run order
+      int64_t run = total;
+      for (size_t i = segs.size() - (size_t)(ceil4(L) * ngroups); i < segs.size(); i++) {
+        segs[i].block0 = (int32_t)std::min<int64_t>(run, kMaxBlocks);
+        run += segs[i].nbx;
+      }
+    }
+    total += cb;
+    if (total > kMaxBlocks) {
+      delete p;
+      return ZFPX_EINVAL;
+    }
+  }
+  p->chunk_first[nchunks] = total;
+  p->nblocks = total;
+  p->nvalues = values;
+  p->min_elems = min_elems;
+  p->vec4 = vec4;
+  p->shape_key = {nchunks, total, values, (int64_t)segs.size()};
+
+  // run starts and the tile -> run table
+  seg_block0.resize(segs.size() + 1);
+  for (size_t i = 0; i < segs.size(); i++) seg_block0[i] = segs[i].block0;
+  seg_block0[segs.size()] = (int32_t)total;
+  int64_t ntiles = (total + 63) / 64;
+  std::vector<int32_t> tile_seg(std::max<int64_t>(ntiles, 1), 0);
+  size_t s = 0;
+  for (int64_t t = 0; t < ntiles; t++) {
+    int64_t b = 64 * t;
+    while (s + 1 < segs.size() && seg_block0[s + 1] <= b) s++;
+    tile_seg[t] = (int32_t)s;
+  }
+  if (!segs.empty()) {
+    size_t nseg = segs.size();
+    if (hipMalloc(&p->d_segs, nseg * sizeof(SegDesc)) != hipSuccess ||
+        hipMalloc(&p->d_seg_block0, (nseg + 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&p->d_tile_seg, tile_seg.size() * sizeof(int32_t)) != hipSuccess) {
+      zfpx_plan_destroy(p);
+      return ZFPX_ENOMEM;
+    }
+    if (hipMemcpy(p->d_segs, segs.data(), nseg * sizeof(SegDesc), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(p->d_seg_block0, seg_block0.data(), (nseg + 1) * sizeof(int32_t),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_tile_seg, tile_seg.data(), tile_seg.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      zfpx_plan_destroy(p);
+      return ZFPX_EHIP;
+    }
+  }
+  p->dev = PlanDev{p->d_segs, p->d_seg_block0, p->d_tile_seg};
+  (void)device_cu_count();  // device facts are queried here, outside any capture
+  *out = p;
+  return ZFPX_OK;
+}
+
+int zfpx_plan_info(const zfpx_plan* p, int64_t* nblocks, int64_t* nvalues,
+                   int64_t* min_buffer_elems) {
+  if (!p) return ZFPX_EINVAL;
+  if (nblocks) *nblocks = p->nblocks;
+  if (nvalues) *nvalues = p->nvalues;
+  if (min_buffer_elems) *min_buffer_elems = p->min_elems;
+  return ZFPX_OK;
+}
+
+int zfpx_plan_sizes(const zfpx_plan* p, int rate, int64_t* chunk_bytes, int64_t* chunk_offsets,
+                    int64_t* total_bytes) {
+  if (!p || !rate_ok(rate)) return ZFPX_EINVAL;
+  for (int c = 0; c < p->nchunks; c++) {
+    if (chunk_bytes) chunk_bytes[c] = p->chunk_blocks[c] * 8 * rate;
+    if (chunk_offsets) chunk_offsets[c] = p->chunk_first[c] * 8 * rate;
+  }
+  if (total_bytes) *total_bytes = p->nblocks * 8 * rate;
+  return ZFPX_OK;
+}
+
+static int plan_range(const zfpx_plan* p, int32_t first, int32_t count, int32_t* b0,
+                      int32_t* b1) {
+  if (first < 0 || count < 0 || (int64_t)first + count > p->nchunks) return ZFPX_EINVAL;
+  *b0 = (int32_t)p->chunk_first[first];
+  *b1 = (int32_t)p->chunk_first[first + count];
+  return ZFPX_OK;
+}
+
+static int do_pack_encode(const zfpx_plan* p, int32_t first, int32_t count, const float* d_src,
+                          int64_t src_elems, int rate, void* d_send, size_t send_bytes,
+                          void* stream) {
+  if (!p || !rate_ok(rate)) return ZFPX_EINVAL;
+  int32_t b0, b1;
+  int st = plan_range(p, first, count, &b0, &b1);
+  if (st) return st;
+  if (b1 == b0) return ZFPX_OK;
+  if (!d_src || !d_send || !aligned(d_send, 8) || src_elems < p->min_elems) return ZFPX_EINVAL;
+  if ((int64_t)send_bytes < p->nblocks * 8 * rate) return ZFPX_ENOSPC;
+  bool vec4 = p->vec4 && aligned(d_src, 16);
+  hipError_t e = launch_plan_encode(p->dev, vec4, d_src, (uint64_t*)d_send, rate, b0, b1,
+                                    p->config(kOpEncode, rate), (hipStream_t)stream);
+  return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
+}
+
+static int do_decode_unpack(const zfpx_plan* p, int32_t first, int32_t count, const void* d_recv,
+                            size_t recv_bytes, int rate, float* d_dst, int64_t dst_elems,
+                            void* stream) {
+  if (!p || !rate_ok(rate)) return ZFPX_EINVAL;
+  int32_t b0, b1;
+  int st = plan_range(p, first, count, &b0, &b1);
+  if (st) return st;
+  if (b1 == b0) return ZFPX_OK;
+  if (!d_recv || !d_dst || !aligned(d_recv, 8) || dst_elems < p->min_elems) return ZFPX_EINVAL;
+  if ((int64_t)recv_bytes < p->nblocks * 8 * rate) return ZFPX_ENOSPC;
+  bool vec4 = p->vec4 && aligned(d_dst, 16);
+  hipError_t e = launch_plan_decode(p->dev, vec4, (const uint64_t*)d_recv, d_dst, rate, b0, b1,
+                                    p->config(kOpDecode, rate), (hipStream_t)stream);
+  return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
+}
+
+int zfpx_pack_encode(const zfpx_plan* p, const float* d_src, int64_t src_elems, int rate,
+                     void* d_send, size_t send_bytes, void* stream) {
+  if (!p) return ZFPX_EINVAL;
+  return do_pack_encode(p, 0, p->nchunks, d_src, src_elems, rate, d_send, send_bytes, stream);
+}
+
+int zfpx_decode_unpack(const zfpx_plan* p, const void* d_recv, size_t recv_bytes, int rate,
+                       float* d_dst, int64_t dst_elems, void* stream) {
+  if (!p) return ZFPX_EINVAL;
+  return do_decode_unpack(p, 0, p->nchunks, d_recv, recv_bytes, rate, d_dst, dst_elems, stream);
+}
+
+int zfpx_pack_encode_chunks(const zfpx_plan* p, int32_t first, int32_t count, const float* d_src,
+                            int64_t src_elems, int rate, void* d_send, size_t send_bytes,
+                            void* stream) {
+  return do_pack_encode(p, first, count, d_src, src_elems, rate, d_send, send_bytes, stream);
+}
+
+int zfpx_decode_unpack_chunks(const zfpx_plan* p, int32_t first, int32_t count,
+                              const void* d_recv, size_t recv_bytes, int rate, float* d_dst,
+                              int64_t dst_elems, void* stream) {
+  return do_decode_unpack(p, first, count, d_recv, recv_bytes, rate, d_dst, dst_elems, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Launch configuration and autotuning
+// ---------------------------------------------------------------------------
+
+int zfpx_plan_set_config(zfpx_plan* p, int op, int rate, int wg_threads, int grid_wgs) {
+  if (!p || (op != kOpEncode && op != kOpDecode) || rate < 0 || rate > 32) return ZFPX_EINVAL;
+  LaunchCfg c;
+  c.wg = wg_threads;
+  c.grid = grid_wgs;
+  if (!cfg_ok(c, rate == 0 ? 1 : rate)) return ZFPX_EINVAL;
+  p->cfg[{op, rate}] = c;
+  return ZFPX_OK;
+}
+
+int zfpx_plan_get_config(const zfpx_plan* p, int op, int rate, int* wg_threads, int* grid_wgs) {
+  if (!p || (op != kOpEncode && op != kOpDecode) || !rate_ok(rate)) return ZFPX_EINVAL;
+  LaunchCfg c = p->config(op, rate);
+  if (wg_threads) *wg_threads = c.wg;
+  if (grid_wgs) *grid_wgs = c.grid;
+  return ZFPX_OK;
+}
+
+static std::string tune_key(const zfpx_plan* p, int op, int rate) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ' || ch == ':') ch = '_';
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s op%d r%d c%lld b%lld v%lld s%lld", arch.c_str(), op, rate,
+           (long long)p->shape_key[0], (long long)p->shape_key[1], (long long)p->shape_key[2],
+           (long long)p->shape_key[3]);
+  return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, LaunchCfg* c) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char* bar = strchr(line, '|');
+    if (!bar) continue;
+    std::string k(line, bar - line);
+    int wg = 0, grid = 0;
+    if (k == key && sscanf(bar + 1, "%d %d", &wg, &grid) == 2) {
+      c->wg = wg;
+      c->grid = grid;
+      found = true;  // the last entry wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+static void cache_store(const char* path, const std::string& key, LaunchCfg c, double us) {
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s|%d %d %.3f\n", key.c_str(), c.wg, c.grid, us);
+  fclose(f);
+}
+
+int zfpx_autotune(zfpx_plan* p, int op, int rate, const float* d_src, int64_t src_elems,
+                  void* d_stream_buf, size_t stream_bytes, float* d_dst, int64_t dst_elems,
+                  const char* cache_path, void* stream, double* best_us) {
+  if (!p || !rate_ok(rate) || (op != kOpEncode && op != kOpDecode)) return ZFPX_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::string key = tune_key(p, op, rate);
+  LaunchCfg cached;
+  if (cache_lookup(cache_path, key, &cached) && cfg_ok(cached, rate)) {
+    p->cfg[{op, rate}] = cached;
+    if (best_us) *best_us = -1.0;
+    return ZFPX_OK;
+  }
+  int cus = device_cu_count();
+  std::vector<LaunchCfg> cands;
+  for (int wg : {64, 128, 256})
+    for (int mult : {0, 1, 2, 4, 8, 16}) {
+      LaunchCfg c;
+      c.wg = wg;
+      c.grid = mult == 0 ? 0 : mult * cus * 4 / (wg / 64);  // waves per CU = 4 * mult
+      if (cfg_ok(c, rate)) cands.push_back(c);
+    }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return ZFPX_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return ZFPX_EHIP;
+  }
+  auto saved = p->cfg;
+  double best = 1e300;
+  LaunchCfg best_c = default_cfg(rate);
+  int st = ZFPX_OK;
+  for (const LaunchCfg& c : cands) {
+    p->cfg[{op, rate}] = c;
+    auto run = [&]() {
+      return op == kOpEncode
+                 ? zfpx_pack_encode(p, d_src, src_elems, rate, d_stream_buf, stream_bytes, s)
+                 : zfpx_decode_unpack(p, d_stream_buf, stream_bytes, rate, d_dst, dst_elems, s);
+    };
+    for (int i = 0; i < 2 && st == ZFPX_OK; i++) st = run();
+    if (st) break;
+    const int reps = 5;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = ZFPX_EHIP; break; }
+    for (int i = 0; i < reps && st == ZFPX_OK; i++) st = run();
+    if (st) break;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      st = ZFPX_EHIP;
+      break;
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    double us = 1000.0 * ms / reps;
+    if (us < best) {
+      best = us;
+      best_c = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    p->cfg = saved;
+    return st;
+  }
+  p->cfg[{op, rate}] = best_c;
+  cache_store(cache_path, key, best_c, best);
+  if (best_us) *best_us = best;
+  return ZFPX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graphs
+// ---------------------------------------------------------------------------
+
+int zfpx_graph_destroy(zfpx_graph* g) {
+  if (!g) return ZFPX_EINVAL;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return ZFPX_OK;
+}
+
+int zfpx_graph_create(const zfpx_plan* p, int rate, const float* d_src, int64_t src_elems,
+                      void* d_send, size_t send_bytes, float* d_dst, int64_t dst_elems,
+                      zfpx_graph** out) {
+  if (!p || !out || !rate_ok(rate)) return ZFPX_EINVAL;
+  *out = nullptr;
+  if (!d_src || !d_send || !d_dst) return ZFPX_EINVAL;
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return ZFPX_EHIP;
+  zfpx_graph* g = new (std::nothrow) zfpx_graph();
+  if (!g) {
+    (void)hipStreamDestroy(cs);
+    return ZFPX_ENOMEM;
+  }
+  int st = ZFPX_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    st = ZFPX_EHIP;
+  } else {
+    st = zfpx_pack_encode(p, d_src, src_elems, rate, d_send, send_bytes, cs);
+    if (st == ZFPX_OK)
+      st = zfpx_decode_unpack(p, d_send, send_bytes, rate, d_dst, dst_elems, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    g->graph = graph;
+    if (st == ZFPX_OK && e != hipSuccess) st = ZFPX_EHIP;
+    if (st == ZFPX_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+      st = ZFPX_EHIP;
+  }
+  (void)hipStreamDestroy(cs);
+  if (st) {
+    zfpx_graph_destroy(g);
+    return st;
+  }
+  *out = g;
+  return ZFPX_OK;
+}
+
+int zfpx_graph_launch(zfpx_graph* g, void* stream) {
+  if (!g || !g->exec) return ZFPX_EINVAL;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// float16 comparator
+// ---------------------------------------------------------------------------
+
+int f16_truncate(const float* d_in, size_t n, uint16_t* d_out, void* stream) {
+  if (n == 0) return ZFPX_OK;
+  if (!d_in || !d_out || !aligned(d_in, 4) || !aligned(d_out, 2)) return ZFPX_EINVAL;
+  return launch_f16_truncate(d_in, n, d_out, (hipStream_t)stream) == hipSuccess ? ZFPX_OK
+                                                                                 : ZFPX_EHIP;
+}
+
+int f16_restore(const uint16_t* d_in, size_t n, float* d_out, void* stream) {
+  if (n == 0) return ZFPX_OK;
+  if (!d_in || !d_out || !aligned(d_in, 2) || !aligned(d_out, 4)) return ZFPX_EINVAL;
+  return launch_f16_restore(d_in, n, d_out, (hipStream_t)stream) == hipSuccess ? ZFPX_OK
+                                                                                : ZFPX_EHIP;
+}
+
+}  // extern "C"

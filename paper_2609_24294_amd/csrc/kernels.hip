@@ -1,0 +1,410 @@
+// kernels.hip -- HIP kernels for gfx950: fused gather + encode, decode +
+// scatter, and the float16 comparator.
+//
+// Mapping.  One 4x4x4 block per lane; one wavefront handles a tile of 64
+// consecutive blocks (consecutive x blocks of a row group, so the 16 row
+// segments a lane reads are contiguous 16-byte pieces and a wavefront's loads
+// of one row are one contiguous 1 KiB stretch).  The coded words of a tile are
+// contiguous in the output, so each lane codes into its own slice of LDS
+// (stride rate|1 words to spread the banks) and the wavefront then copies the
+// tile out (or in, for decoding) with coalesced 8-byte accesses.  Workgroups
+// loop over tiles with a grid stride, so the same kernel serves as a
+// one-tile-per-wave launch and as a persistent launch.
+#include <hip/hip_runtime.h>
+
+#include "block_codec.hpp"
+#include "internal.hpp"
+
+namespace zfpx {
+
+// ---------------------------------------------------------------------------
+// Block location
+// ---------------------------------------------------------------------------
+
+struct BlockView {
+  int64_t rbase[4];
+  int64_t lstride;
+  int64_t sx;
+  int32_t nlev, nrow;
+  int32_t rlen[4];
+  int32_t x0;  // first x of the block
+};
+
+struct PlanGeo {
+  PlanDev p;
+  __device__ __forceinline__ void locate(int32_t b, BlockView& v) const {
+    int32_t s = p.tile_seg[b >> 6];
+    while (p.seg_block0[s + 1] <= b) s++;
+    const SegDesc& d = p.segs[s];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      v.rbase[i] = d.rbase[i];
+      v.rlen[i] = d.rlen[i];
+    }
+    v.lstride = d.lstride;
+    v.sx = 1;
+    v.nlev = d.nlev;
+    v.nrow = d.nrow;
+    v.x0 = 4 * (b - d.block0);
+  }
+};
+
+struct RegularGeo {
+  RegularDev g;
+  __device__ __forceinline__ void locate(int32_t b, BlockView& v) const {
+    uint32_t ub = (uint32_t)b;
+    uint32_t t = ub / (uint32_t)g.nbx;
+    uint32_t bx = ub - t * (uint32_t)g.nbx;
+    uint32_t bz = t / (uint32_t)g.nby;
+    uint32_t by = t - bz * (uint32_t)g.nby;
+    int64_t y0 = 4 * (int64_t)by, z0 = 4 * (int64_t)bz;
+    int64_t zoff = z0 * g.sz;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      int64_t y = y0 + i < g.ny ? y0 + i : g.ny - 1;
+      v.rbase[i] = zoff + y * g.sy;
+      v.rlen[i] = (int32_t)g.nx;
+    }
+    v.lstride = g.sz;
+    v.sx = g.sx;
+    v.nlev = (int32_t)(g.nz - z0 < 4 ? g.nz - z0 : 4);
+    v.nrow = (int32_t)(g.ny - y0 < 4 ? g.ny - y0 : 4);
+    v.x0 = (int32_t)(4 * bx);
+  }
+};
+
+template <bool VEC4>
+__device__ __forceinline__ void gather(const float* __restrict__ src, const BlockView& v,
+                                       float* val) {
+#pragma unroll
+  for (int dz = 0; dz < 4; dz++) {
+    int64_t zoff = (int64_t)(dz < v.nlev ? dz : v.nlev - 1) * v.lstride;
+#pragma unroll
+    for (int dy = 0; dy < 4; dy++) {
+      int64_t base = v.rbase[dy] + zoff;
+      int len = v.rlen[dy];
+      float* o = val + 16 * dz + 4 * dy;
+      if (VEC4 && v.x0 + 3 < len) {
+        float4 f = *reinterpret_cast<const float4*>(src + base + v.x0);
+        o[0] = f.x;
+        o[1] = f.y;
+        o[2] = f.z;
+        o[3] = f.w;
+      } else {
+#pragma unroll
+        for (int dx = 0; dx < 4; dx++) {
+          int x = v.x0 + dx < len ? v.x0 + dx : len - 1;
+          o[dx] = src[base + (int64_t)x * v.sx];
+        }
+      }
+    }
+  }
+}
+
+template <bool VEC4>
+__device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView& v,
+                                        const float* val) {
+#pragma unroll
+  for (int dz = 0; dz < 4; dz++) {
+    if (dz < v.nlev) {
+      int64_t zoff = (int64_t)dz * v.lstride;
+#pragma unroll
+      for (int dy = 0; dy < 4; dy++) {
+        if (dy < v.nrow) {
+          int64_t base = v.rbase[dy] + zoff;
+          int len = v.rlen[dy];
+          const float* o = val + 16 * dz + 4 * dy;
+          if (VEC4 && v.x0 + 3 < len) {
+            *reinterpret_cast<float4*>(dst + base + v.x0) = make_float4(o[0], o[1], o[2], o[3]);
+          } else {
+#pragma unroll
+            for (int dx = 0; dx < 4; dx++)
+              if (v.x0 + dx < len) dst[base + (int64_t)(v.x0 + dx) * v.sx] = o[dx];
+          }
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__host__ __device__ constexpr int lds_stride(int rate) { return rate | 1; }
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+template <int RATE, bool VEC4, class Geo>
+__global__ __launch_bounds__(256) void k_encode(Geo geo, const float* __restrict__ src,
+                                                uint64_t* __restrict__ out, int rate_rt,
+                                                int32_t b_begin, int32_t b_end) {
+  extern __shared__ uint64_t lds[];
+  const int rate = RATE > 0 ? RATE : rate_rt;
+  const int stride = lds_stride(rate);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  uint64_t* wlds = lds + (size_t)wave * 64 * stride;
+  const int32_t nblk = b_end - b_begin;
+  const int32_t ntiles = (nblk + 63) >> 6;
+  for (int32_t t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
+    const int32_t b0 = b_begin + (t << 6);
+    const int32_t b = b0 + lane;
+    const int nact = b_end - b0 < 64 ? b_end - b0 : 64;
+    if (lane < nact) {
+      BlockView v;
+      geo.locate(b, v);
+      float val[64];
+      gather<VEC4>(src, v, val);
+      encode_block<RATE>(val, wlds + lane * stride, rate);
+    }
+    wave_sync_lds();
+    uint64_t* o = out + (int64_t)b0 * rate;
+    const int nw = nact * rate;
+    for (int w = lane; w < nw; w += 64) {
+      int blk = w / rate;
+      int idx = w - blk * rate;
+      o[w] = wlds[blk * stride + idx];
+    }
+    wave_sync_lds();
+  }
+}
+
+template <int RATE, bool VEC4, class Geo>
+__global__ __launch_bounds__(256) void k_decode(Geo geo, const uint64_t* __restrict__ in,
+                                                float* __restrict__ dst, int rate_rt,
+                                                int32_t b_begin, int32_t b_end) {
+  extern __shared__ uint64_t lds[];
+  const int rate = RATE > 0 ? RATE : rate_rt;
+  const int stride = lds_stride(rate);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  uint64_t* wlds = lds + (size_t)wave * 64 * stride;
+  const int32_t nblk = b_end - b_begin;
+  const int32_t ntiles = (nblk + 63) >> 6;
+  for (int32_t t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
+    const int32_t b0 = b_begin + (t << 6);
+    const int32_t b = b0 + lane;
+    const int nact = b_end - b0 < 64 ? b_end - b0 : 64;
+    const uint64_t* ip = in + (int64_t)b0 * rate;
+    const int nw = nact * rate;
+    for (int w = lane; w < nw; w += 64) {
+      int blk = w / rate;
+      int idx = w - blk * rate;
+      wlds[blk * stride + idx] = ip[w];
+    }
+    wave_sync_lds();
+    if (lane < nact) {
+      float val[64];
+      decode_block<RATE>(wlds + lane * stride, val, rate);
+      BlockView v;
+      geo.locate(b, v);
+      scatter<VEC4>(dst, v, val);
+    }
+    wave_sync_lds();
+  }
+}
+
+// float16 comparator: 8 values per thread per step when aligned.
+__global__ __launch_bounds__(256) void k_f16_truncate_v8(const float4* __restrict__ in,
+                                                         size_t n8, uint4* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8;
+       i += (size_t)gridDim.x * blockDim.x) {
+    float4 a = in[2 * i], b = in[2 * i + 1];
+    auto h = [](float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f); };
+    uint4 r;
+    r.x = h(a.x) | (h(a.y) << 16);
+    r.y = h(a.z) | (h(a.w) << 16);
+    r.z = h(b.x) | (h(b.y) << 16);
+    r.w = h(b.z) | (h(b.w) << 16);
+    out[i] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_f16_truncate_s(const float* __restrict__ in, size_t n,
+                                                        uint16_t* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = __builtin_bit_cast(uint16_t, (_Float16)in[i]);
+}
+
+__global__ __launch_bounds__(256) void k_f16_restore_v8(const uint4* __restrict__ in, size_t n8,
+                                                        float4* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8;
+       i += (size_t)gridDim.x * blockDim.x) {
+    uint4 r = in[i];
+    auto f = [](uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)w); };
+    out[2 * i] = make_float4(f(r.x), f(r.x >> 16), f(r.y), f(r.y >> 16));
+    out[2 * i + 1] = make_float4(f(r.z), f(r.z >> 16), f(r.w), f(r.w >> 16));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_f16_restore_s(const uint16_t* __restrict__ in, size_t n,
+                                                       float* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = (float)__builtin_bit_cast(_Float16, in[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+size_t lds_bytes(int wg, int rate) {
+  return (size_t)(wg / 64) * 64 * lds_stride(rate) * sizeof(uint64_t);
+}
+
+static int g_cus = -1;
+static size_t g_max_lds = 0;
+
+static void query_device() {
+  if (g_cus >= 0) return;
+  int dev = 0, cus = 0, lds = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  }
+  g_cus = cus > 0 ? cus : 256;
+  g_max_lds = lds > 0 ? (size_t)lds : 65536;
+}
+
+size_t device_max_lds() {
+  query_device();
+  return g_max_lds;
+}
+
+int device_cu_count() {
+  query_device();
+  return g_cus;
+}
+
+static dim3 grid_for(int32_t nblocks, LaunchCfg cfg) {
+  int waves = cfg.wg / 64;
+  int64_t ntiles = ((int64_t)nblocks + 63) / 64;
+  int64_t full = (ntiles + waves - 1) / waves;
+  int64_t g = cfg.grid > 0 && cfg.grid < full ? cfg.grid : full;
+  return dim3((unsigned)(g > 0 ? g : 1));
+}
+
+#define ZFPX_RATE_SWITCH(KERNEL, GEO, VEC4, ...)                                         \
+  switch (rate) {                                                                          \
+    case 8:                                                                                \
+      hipLaunchKernelGGL((KERNEL<8, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);        \
+      break;                                                                               \
+    case 16:                                                                               \
+      hipLaunchKernelGGL((KERNEL<16, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);       \
+      break;                                                                               \
+    case 32:                                                                               \
+      hipLaunchKernelGGL((KERNEL<32, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);       \
+      break;                                                                               \
+    default:                                                                               \
+      hipLaunchKernelGGL((KERNEL<0, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);        \
+      break;                                                                               \
+  }
+
+hipError_t launch_plan_encode(const PlanDev& p, bool vec4, const float* src, uint64_t* out,
+                              int rate, int32_t b_begin, int32_t b_end, LaunchCfg cfg,
+                              hipStream_t s) {
+  if (b_end <= b_begin) return hipSuccess;
+  dim3 grid = grid_for(b_end - b_begin, cfg), block(cfg.wg);
+  size_t shm = lds_bytes(cfg.wg, rate);
+  PlanGeo geo{p};
+  if (vec4) {
+    ZFPX_RATE_SWITCH(k_encode, PlanGeo, true, geo, src, out, rate, b_begin, b_end);
+  } else {
+    ZFPX_RATE_SWITCH(k_encode, PlanGeo, false, geo, src, out, rate, b_begin, b_end);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_decode(const PlanDev& p, bool vec4, const uint64_t* in, float* dst,
+                              int rate, int32_t b_begin, int32_t b_end, LaunchCfg cfg,
+                              hipStream_t s) {
+  if (b_end <= b_begin) return hipSuccess;
+  dim3 grid = grid_for(b_end - b_begin, cfg), block(cfg.wg);
+  size_t shm = lds_bytes(cfg.wg, rate);
+  PlanGeo geo{p};
+  if (vec4) {
+    ZFPX_RATE_SWITCH(k_decode, PlanGeo, true, geo, in, dst, rate, b_begin, b_end);
+  } else {
+    ZFPX_RATE_SWITCH(k_decode, PlanGeo, false, geo, in, dst, rate, b_begin, b_end);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_regular_encode(const RegularDev& g, bool vec4, const float* src,
+                                 uint64_t* out, int rate, int32_t nblocks, LaunchCfg cfg,
+                                 hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  dim3 grid = grid_for(nblocks, cfg), block(cfg.wg);
+  size_t shm = lds_bytes(cfg.wg, rate);
+  RegularGeo geo{g};
+  int32_t b0 = 0;
+  if (vec4) {
+    ZFPX_RATE_SWITCH(k_encode, RegularGeo, true, geo, src, out, rate, b0, nblocks);
+  } else {
+    ZFPX_RATE_SWITCH(k_encode, RegularGeo, false, geo, src, out, rate, b0, nblocks);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_regular_decode(const RegularDev& g, bool vec4, const uint64_t* in, float* dst,
+                                 int rate, int32_t nblocks, LaunchCfg cfg, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  dim3 grid = grid_for(nblocks, cfg), block(cfg.wg);
+  size_t shm = lds_bytes(cfg.wg, rate);
+  RegularGeo geo{g};
+  int32_t b0 = 0;
+  if (vec4) {
+    ZFPX_RATE_SWITCH(k_decode, RegularGeo, true, geo, in, dst, rate, b0, nblocks);
+  } else {
+    ZFPX_RATE_SWITCH(k_decode, RegularGeo, false, geo, in, dst, rate, b0, nblocks);
+  }
+  return hipGetLastError();
+}
+
+static unsigned elementwise_grid(size_t work) {
+  query_device();
+  size_t g = (work + 255) / 256;
+  size_t cap = (size_t)g_cus * 16;
+  if (g > cap) g = cap;
+  return (unsigned)(g > 0 ? g : 1);
+}
+
+hipError_t launch_f16_truncate(const float* in, size_t n, uint16_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t done = 0;
+  if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0 && n >= 8) {
+    size_t n8 = n / 8;
+    hipLaunchKernelGGL(k_f16_truncate_v8, dim3(elementwise_grid(n8)), dim3(256), 0, s,
+                       reinterpret_cast<const float4*>(in), n8, reinterpret_cast<uint4*>(out));
+    done = n8 * 8;
+  }
+  if (done < n)
+    hipLaunchKernelGGL(k_f16_truncate_s, dim3(elementwise_grid(n - done)), dim3(256), 0, s,
+                       in + done, n - done, out + done);
+  return hipGetLastError();
+}
+
+hipError_t launch_f16_restore(const uint16_t* in, size_t n, float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t done = 0;
+  if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0 && n >= 8) {
+    size_t n8 = n / 8;
+    hipLaunchKernelGGL(k_f16_restore_v8, dim3(elementwise_grid(n8)), dim3(256), 0, s,
+                       reinterpret_cast<const uint4*>(in), n8, reinterpret_cast<float4*>(out));
+    done = n8 * 8;
+  }
+  if (done < n)
+    hipLaunchKernelGGL(k_f16_restore_s, dim3(elementwise_grid(n - done)), dim3(256), 0, s,
+                       in + done, n - done, out + done);
+  return hipGetLastError();
+}
+
+}  // namespace zfpx

@@ -1,0 +1,322 @@
+"""Thin ctypes binding of libzfpx.so (declared in include/zfpx.h).
+
+Argument marshalling only: every step of the coding runs in the HIP
+kernels of the library.  PyTorch supplies device memory (tensors) and
+streams; the functions take CUDA/HIP tensors and pass their device pointers
+and the current HIP stream through the C ABI.  There is no fallback: if the
+library is not built, importing this module raises.
+
+Compressed streams are held in int64 tensors (one element per 64-bit word).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime that the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libzfpx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(or python -m paper_2609_24294_amd.build)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_c = ctypes
+_P = _c.c_void_p
+_I64 = _c.c_int64
+_I32 = _c.c_int32
+_INT = _c.c_int
+_SZ = _c.c_size_t
+_PI64 = _c.POINTER(_c.c_int64)
+_PI32 = _c.POINTER(_c.c_int32)
+
+_SIGS = {
+    "zfpx_status_string": (_c.c_char_p, [_INT]),
+    "zfpx_version": (_INT, []),
+    "zfpx_device_cus": (_INT, []),
+    "zfpx_fixed_rate_bytes": (_I64, [_I64, _I64, _I64, _INT]),
+    "zfpx_encode_fixed_rate": (_INT, [_P, _I64, _I64, _I64, _I64, _I64, _I64, _INT, _P, _SZ, _P]),
+    "zfpx_decode_fixed_rate": (_INT, [_P, _SZ, _I64, _I64, _I64, _I64, _I64, _I64, _INT, _P, _P]),
+    "zfpx_plan_create": (_INT, [_I32, _PI64, _PI64, _PI32, _PI32, _PI64, _PI32, _c.POINTER(_P)]),
+    "zfpx_plan_destroy": (_INT, [_P]),
+    "zfpx_plan_info": (_INT, [_P, _PI64, _PI64, _PI64]),
+    "zfpx_plan_sizes": (_INT, [_P, _INT, _PI64, _PI64, _PI64]),
+    "zfpx_pack_encode": (_INT, [_P, _P, _I64, _INT, _P, _SZ, _P]),
+    "zfpx_decode_unpack": (_INT, [_P, _P, _SZ, _INT, _P, _I64, _P]),
+    "zfpx_pack_encode_chunks": (_INT, [_P, _I32, _I32, _P, _I64, _INT, _P, _SZ, _P]),
+    "zfpx_decode_unpack_chunks": (_INT, [_P, _I32, _I32, _P, _SZ, _INT, _P, _I64, _P]),
+    "zfpx_plan_set_config": (_INT, [_P, _INT, _INT, _INT, _INT]),
+    "zfpx_plan_get_config": (_INT, [_P, _INT, _INT, _c.POINTER(_INT), _c.POINTER(_INT)]),
+    "zfpx_autotune": (_INT, [_P, _INT, _INT, _P, _I64, _P, _SZ, _P, _I64, _c.c_char_p, _P,
+                             _c.POINTER(_c.c_double)]),
+    "zfpx_graph_create": (_INT, [_P, _INT, _P, _I64, _P, _SZ, _P, _I64, _c.POINTER(_P)]),
+    "zfpx_graph_launch": (_INT, [_P, _P]),
+    "zfpx_graph_destroy": (_INT, [_P]),
+    "f16_truncate": (_INT, [_P, _SZ, _P, _P]),
+    "f16_restore": (_INT, [_P, _SZ, _P, _P]),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+OK, EINVAL, ENOSPC, EHIP, ENOMEM, EAGAIN, ESTATE = 0, -1, -2, -3, -4, -5, -6
+OP_ENCODE, OP_DECODE = 0, 1
+
+
+class ZfpxError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {zfpx_status_string(status)} ({status})")
+
+
+def zfpx_status_string(status: int) -> str:
+    return _lib.zfpx_status_string(int(status)).decode()
+
+
+def _check(st: int, where: str) -> None:
+    if st != OK:
+        raise ZfpxError(st, where)
+
+
+def library():
+    """The loaded ctypes library (for calls with raw pointers)."""
+    return _lib
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def _dev(t: torch.Tensor, dtype=None) -> int:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
+def zfpx_version() -> int:
+    return _lib.zfpx_version()
+
+
+def zfpx_device_cus() -> int:
+    return _lib.zfpx_device_cus()
+
+
+# ---------------------------------------------------------------------------
+# Regular arrays
+# ---------------------------------------------------------------------------
+
+def zfpx_fixed_rate_bytes(nx: int, ny: int, nz: int, rate: int) -> int:
+    n = _lib.zfpx_fixed_rate_bytes(nx, ny, nz, rate)
+    _check(n if n < 0 else 0, "zfpx_fixed_rate_bytes")
+    return n
+
+
+def zfpx_encode_fixed_rate(src: torch.Tensor, rate: int, out: torch.Tensor | None = None,
+                           stream=None) -> torch.Tensor:
+    """Encode a (nz, ny, nx) float32 device tensor (any strides)."""
+    nz, ny, nx = src.shape
+    sz, sy, sx = src.stride()
+    nbytes = zfpx_fixed_rate_bytes(nx, ny, nz, rate)
+    if out is None:
+        out = torch.empty(nbytes // 8, dtype=torch.int64, device=src.device)
+    _check(_lib.zfpx_encode_fixed_rate(_dev(src, torch.float32), nx, ny, nz, sx, sy, sz, rate,
+                                       _dev(out), _nbytes(out), _stream(stream)),
+           "zfpx_encode_fixed_rate")
+    return out
+
+
+def zfpx_decode_fixed_rate(words: torch.Tensor, rate: int, out: torch.Tensor, stream=None):
+    """Decode into `out`, a (nz, ny, nx) float32 device tensor (any strides)."""
+    nz, ny, nx = out.shape
+    sz, sy, sx = out.stride()
+    _check(_lib.zfpx_decode_fixed_rate(_dev(words), _nbytes(words), nx, ny, nz, sx, sy, sz, rate,
+                                       _dev(out, torch.float32), _stream(stream)),
+           "zfpx_decode_fixed_rate")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Plans
+# ---------------------------------------------------------------------------
+
+def _arr(a, ctype):
+    import numpy as np
+    dt = np.int64 if ctype is _c.c_int64 else np.int32
+    a = np.ascontiguousarray(a, dtype=dt)
+    return a, a.ctypes.data_as(_c.POINTER(ctype))
+
+
+class Plan:
+    """Owns a zfpx_plan built from chunk tables (see include/zfpx.h)."""
+
+    def __init__(self, chunk_base, level_stride, levels, row_start, row_offset, row_len):
+        keep = []
+        args = []
+        for a, ct in ((chunk_base, _I64), (level_stride, _I64), (levels, _I32),
+                      (row_start, _I32), (row_offset, _I64), (row_len, _I32)):
+            arr, ptr = _arr(a, ct)
+            keep.append(arr)
+            args.append(ptr)
+        self.nchunks = int(keep[0].size)
+        h = _P()
+        _check(_lib.zfpx_plan_create(self.nchunks, *args, _c.byref(h)), "zfpx_plan_create")
+        self._h = h
+        nb, nv, ne = _I64(), _I64(), _I64()
+        _check(_lib.zfpx_plan_info(h, _c.byref(nb), _c.byref(nv), _c.byref(ne)), "zfpx_plan_info")
+        self.nblocks, self.nvalues, self.min_buffer_elems = nb.value, nv.value, ne.value
+
+    @classmethod
+    def from_chunkset(cls, cs) -> "Plan":
+        return cls(cs.chunk_base, cs.level_stride, cs.levels, cs.row_start, cs.row_offset,
+                   cs.row_len)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sizes(self, rate: int):
+        """(per-chunk bytes, per-chunk offsets, total bytes)."""
+        import numpy as np
+        b = np.zeros(max(self.nchunks, 1), np.int64)
+        o = np.zeros(max(self.nchunks, 1), np.int64)
+        t = _I64()
+        _check(_lib.zfpx_plan_sizes(self._h, rate, b.ctypes.data_as(_PI64),
+                                    o.ctypes.data_as(_PI64), _c.byref(t)), "zfpx_plan_sizes")
+        return b[: self.nchunks], o[: self.nchunks], t.value
+
+    def total_bytes(self, rate: int) -> int:
+        return self.nblocks * 8 * rate
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.zfpx_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def zfpx_plan_create(chunks) -> Plan:
+    return Plan.from_chunkset(chunks)
+
+
+def zfpx_pack_encode(plan: Plan, src: torch.Tensor, rate: int, send: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    if send is None:
+        send = torch.empty(plan.nblocks * rate, dtype=torch.int64, device=src.device)
+    _check(_lib.zfpx_pack_encode(plan.handle, _dev(src, torch.float32), src.numel(), rate,
+                                 _dev(send), _nbytes(send), _stream(stream)), "zfpx_pack_encode")
+    return send
+
+
+def zfpx_decode_unpack(plan: Plan, recv: torch.Tensor, rate: int, dst: torch.Tensor,
+                       stream=None) -> torch.Tensor:
+    _check(_lib.zfpx_decode_unpack(plan.handle, _dev(recv), _nbytes(recv), rate,
+                                   _dev(dst, torch.float32), dst.numel(), _stream(stream)),
+           "zfpx_decode_unpack")
+    return dst
+
+
+def zfpx_pack_encode_chunks(plan: Plan, first: int, count: int, src: torch.Tensor, rate: int,
+                            send: torch.Tensor, stream=None) -> torch.Tensor:
+    _check(_lib.zfpx_pack_encode_chunks(plan.handle, first, count, _dev(src, torch.float32),
+                                        src.numel(), rate, _dev(send), _nbytes(send),
+                                        _stream(stream)), "zfpx_pack_encode_chunks")
+    return send
+
+
+def zfpx_decode_unpack_chunks(plan: Plan, first: int, count: int, recv: torch.Tensor, rate: int,
+                              dst: torch.Tensor, stream=None) -> torch.Tensor:
+    _check(_lib.zfpx_decode_unpack_chunks(plan.handle, first, count, _dev(recv), _nbytes(recv),
+                                          rate, _dev(dst, torch.float32), dst.numel(),
+                                          _stream(stream)), "zfpx_decode_unpack_chunks")
+    return dst
+
+
+def zfpx_plan_set_config(plan: Plan, op: int, rate: int, wg_threads: int, grid_wgs: int) -> None:
+    _check(_lib.zfpx_plan_set_config(plan.handle, op, rate, wg_threads, grid_wgs),
+           "zfpx_plan_set_config")
+
+
+def zfpx_plan_get_config(plan: Plan, op: int, rate: int):
+    wg, grid = _INT(), _INT()
+    _check(_lib.zfpx_plan_get_config(plan.handle, op, rate, _c.byref(wg), _c.byref(grid)),
+           "zfpx_plan_get_config")
+    return wg.value, grid.value
+
+
+def zfpx_autotune(plan: Plan, op: int, rate: int, src: torch.Tensor, stream_buf: torch.Tensor,
+                  dst: torch.Tensor, cache_path: str | None = None, stream=None) -> float:
+    us = _c.c_double()
+    _check(_lib.zfpx_autotune(plan.handle, op, rate, _dev(src, torch.float32), src.numel(),
+                              _dev(stream_buf), _nbytes(stream_buf), _dev(dst, torch.float32),
+                              dst.numel(), cache_path.encode() if cache_path else None,
+                              _stream(stream), _c.byref(us)), "zfpx_autotune")
+    return us.value
+
+
+class Graph:
+    """pack_encode + decode_unpack over a whole plan, captured in a HIP graph."""
+
+    def __init__(self, plan: Plan, rate: int, src: torch.Tensor, send: torch.Tensor,
+                 dst: torch.Tensor):
+        h = _P()
+        _check(_lib.zfpx_graph_create(plan.handle, rate, _dev(src, torch.float32), src.numel(),
+                                      _dev(send), _nbytes(send), _dev(dst, torch.float32),
+                                      dst.numel(), _c.byref(h)), "zfpx_graph_create")
+        self._h = h
+        self._keep = (plan, src, send, dst)
+
+    def launch(self, stream=None) -> None:
+        _check(_lib.zfpx_graph_launch(self._h, _stream(stream)), "zfpx_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.zfpx_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def zfpx_graph_create(plan, rate, src, send, dst) -> Graph:
+    return Graph(plan, rate, src, send, dst)
+
+
+# ---------------------------------------------------------------------------
+# float16 comparator
+# ---------------------------------------------------------------------------
+
+def f16_truncate(x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(x.numel(), dtype=torch.int16, device=x.device)
+    _check(_lib.f16_truncate(_dev(x, torch.float32), x.numel(), _dev(out), _stream(stream)),
+           "f16_truncate")
+    return out
+
+
+def f16_restore(h: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(h.numel(), dtype=torch.float32, device=h.device)
+    _check(_lib.f16_restore(_dev(h), h.numel(), _dev(out, torch.float32), _stream(stream)),
+           "f16_restore")
+    return out
