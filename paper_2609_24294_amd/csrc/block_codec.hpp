@@ -161,191 +161,175 @@ ZFPX_HD void transpose32(uint32_t* a) {
   transpose_stage<1, 0x55555555u>(a);
 }
 
+// Two independent 32x32 transposes at once on 64-bit words: a[r] holds row r
+// of the first matrix in its low half and of the second in its high half.
+// The stage masks never let a bit cross the 32-bit boundary, so afterwards
+// a[r] low/high bit c = old a[c] low/high bit r.
+template <int J, uint64_t MASK>
+ZFPX_HD void transpose_stage64(uint64_t* a) {
+#pragma unroll
+  for (int r = 0; r < 32; r++) {
+    if ((r & J) == 0) {
+      uint64_t t = ((a[r] >> J) ^ a[r + J]) & MASK;
+      a[r + J] ^= t;
+      a[r] ^= t << J;
+    }
+  }
+}
+
+ZFPX_HD void transpose32x2(uint64_t* a) {
+  transpose_stage64<16, 0x0000ffff0000ffffull>(a);
+  transpose_stage64<8, 0x00ff00ff00ff00ffull>(a);
+  transpose_stage64<4, 0x0f0f0f0f0f0f0f0full>(a);
+  transpose_stage64<2, 0x3333333333333333ull>(a);
+  transpose_stage64<1, 0x5555555555555555ull>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Coded-stream access in LDS
+// ---------------------------------------------------------------------------
+// Each lane owns a slice of LDS words for its block: `rate` words of stream
+// followed by slack words that are always zero, so that windows and writes
+// that run past the budget stay inside the slice.
+
+constexpr int kSlackWords = 2;
+
+// OR the (up to 64-bit) value `code` into the slice at bit position `pos`.
+ZFPX_HD void or_bits(uint64_t* s, uint32_t pos, uint64_t code) {
+  uint32_t w = pos >> 6, b = pos & 63;
+  uint64_t lo = code << b;
+  uint64_t hi = (code >> 1) >> (63 - b);
+#if defined(__HIP_DEVICE_COMPILE__)
+  __hip_atomic_fetch_or(s + w, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  __hip_atomic_fetch_or(s + w + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+#else
+  s[w] |= lo;
+  s[w + 1] |= hi;
+#endif
+}
+
+// The 64 stream bits starting at bit position `pos`.
+ZFPX_HD uint64_t window64(const uint64_t* s, uint32_t pos) {
+  uint32_t w = pos >> 6, b = pos & 63;
+  uint64_t a = s[w], c = s[w + 1];
+  return (a >> b) | ((c << 1) << (63 - b));
+}
+
 // ---------------------------------------------------------------------------
 // Encoder
 // ---------------------------------------------------------------------------
 
-// Bit writer: a 64-bit accumulator flushed word by word to `out`.
-struct BitWriter {
-  uint64_t acc;
-  int na;  // bits held in acc, 0..63
-  int wi;  // words written
-  uint64_t* out;
-
-  ZFPX_HD void put(uint64_t v, int l) {  // 0 <= l <= 64, v < 2^l
-    acc |= v << na;
-    int t = na + l;
-    if (t >= 64) {
-      out[wi++] = acc;
-      acc = na ? (v >> (64 - na)) : 0;
-      t -= 64;
-    }
-    na = t;
-  }
-};
-
-// Encode one block of 64 floats (v[16 z + 4 y + x]) into exactly `rate`
-// 64-bit words written to out[0..rate-1].  v is clobbered.
+// Encode one block of 64 floats (v[16 z + 4 y + x]) into the slice `out`,
+// which must hold rate + kSlackWords zero words.  Bits are ORed in place;
+// the slack words may receive bits past the budget and are not part of the
+// stream.  v is clobbered.
 template <int RATE>
 ZFPX_HD void encode_block(float* v, uint64_t* out, int rate_rt) {
   const int rate = RATE > 0 ? RATE : rate_rt;
-  const int maxbits = 64 * rate;
-  // block exponent: the largest biased exponent field over |v|
-  uint32_t mx = 0;
+  const uint32_t maxbits = 64u * (uint32_t)rate;
+  // block exponent from the largest magnitude (its biased exponent field)
+  float amax = 0.0f;
 #pragma unroll
-  for (int i = 0; i < 64; i++) {
-    uint32_t m = f32_bits(v[i]) & 0x7fffffffu;
-    mx = m > mx ? m : mx;
-  }
-  BitWriter w{0, 0, 0, out};
-  int bits;
-  uint32_t pl[64];  // becomes the plane words: pl[k] low half, pl[32+k] high half
-  if (mx == 0) {
-    w.na = 1;  // single 0 bit
-    bits = 0;
-#pragma unroll
-    for (int i = 0; i < 64; i++) pl[i] = 0;
-  } else {
-    int emax = (int)(mx >> 23) - 126;  // subnormal maximum (field 0) gives -126
-    w.acc = 1u | ((uint64_t)((emax + 127) & 0xff) << 1);
-    w.na = 9;
-    bits = maxbits - 9;
+  for (int i = 0; i < 64; i++) amax = __builtin_fmaxf(amax, __builtin_fabsf(v[i]));
+  uint32_t mx = f32_bits(amax);
+  if (mx == 0) return;  // empty block: the single bit 0, all zero
+  int emax = (int)(mx >> 23) - 126;  // subnormal maximum (field 0) gives -126
+  or_bits(out, 0, 1u | ((uint64_t)((emax + 127) & 0xff) << 1));
+  // X[s] = coefficients s and 32+s (negabinary); after the transpose X[k] is
+  // bit plane k: bit s of X[k] = bit k of coefficient s
+  uint64_t X[32];
+  {
     int32_t q[64];
 #pragma unroll
     for (int i = 0; i < 64; i++) q[i] = (int32_t)scale_pow2(v[i], 30 - emax);
     xform_fwd(q);
 #pragma unroll
-    for (int s = 0; s < 64; s++)
-      pl[s] = ((uint32_t)q[kSeq.idx[s]] + kNegabinaryMask) ^ kNegabinaryMask;
-    transpose32(pl);
-    transpose32(pl + 32);
+    for (int s = 0; s < 32; s++) {
+      uint32_t lo = ((uint32_t)q[kSeq.idx[s]] + kNegabinaryMask) ^ kNegabinaryMask;
+      uint32_t hi = ((uint32_t)q[kSeq.idx[32 + s]] + kNegabinaryMask) ^ kNegabinaryMask;
+      X[s] = (uint64_t)lo | ((uint64_t)hi << 32);
+    }
   }
+  transpose32x2(X);
+  uint32_t pos = 9;
   int n = 0;
 #pragma unroll
   for (int k = 31; k >= 0; k--) {
-    if (bits > 0) {
-      uint64_t x = (uint64_t)pl[k] | ((uint64_t)pl[32 + k] << 32);
-      int m = n < bits ? n : bits;
-      w.put(x & low_mask(m), m);
-      bits -= m;
-      uint64_t y = n < 64 ? (x >> n) : 0;
-      while (n < 64 && bits > 0) {
-        if (y == 0) {  // group test 0: nothing more in this plane
-          w.put(0, 1);
-          bits -= 1;
-          break;
-        }
+    if (pos < maxbits) {
+      uint64_t x = X[k];
+      uint64_t y = n < 64 ? (x >> n) : 0;  // bits not yet significant
+      or_bits(out, pos, x ^ (y << n));     // the first n bits verbatim
+      pos += n;
+      while (y != 0 && pos < maxbits) {
+        // group test 1, zeros up to the next set bit, then that bit (the
+        // bit at position 63 is implied and not written)
         int p = ctz64(y);
-        int last = (n + p == 63);  // the bit at position 63 is implied
-        int len = p + 2 - last;
+        int last = (n + p == 63);
         uint64_t code = last ? uint64_t(1) : (uint64_t(1) | (uint64_t(2) << p));
-        if (len > bits) {
-          len = bits;
-          code &= low_mask(len);
-        }
-        w.put(code, len);
-        bits -= len;
+        or_bits(out, pos, code);
+        pos += p + 2 - last;
         n += p + 1;
-        y = (p >= 63) ? 0 : (y >> (p + 1));
+        y = (y >> p) >> 1;
       }
+      pos += n < 64 ? 1 : 0;  // group test 0 (a zero bit)
     }
   }
-  if (w.na > 0) out[w.wi++] = w.acc;
-  for (int i = w.wi; i < rate; i++) out[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // Decoder
 // ---------------------------------------------------------------------------
 
-// Bit reader over `rate` words with a 64..128-bit window (w0 = next 64 bits).
-struct BitReader {
-  uint64_t w0, w1;
-  int v;   // valid bits in (w0, w1), kept >= 64
-  int ri;  // next word to fetch
-  int nw;  // words in the block
-  const uint64_t* in;
-
-  ZFPX_HD void init(const uint64_t* src, int words) {
-    in = src;
-    nw = words;
-    w0 = src[0];
-    w1 = words > 1 ? src[1] : 0;
-    v = 128;
-    ri = 2;
-  }
-  ZFPX_HD void consume(int l) {  // 0 <= l <= 64
-    if (l == 0) return;
-    if (l < 64) {
-      w0 = (w0 >> l) | (w1 << (64 - l));
-      w1 >>= l;
-    } else {
-      w0 = w1;
-      w1 = 0;
-    }
-    v -= l;
-    if (v < 64) {
-      uint64_t nx = ri < nw ? in[ri] : 0;
-      ri++;
-      w0 |= nx << v;  // v in [0, 63]
-      w1 = v ? (nx >> (64 - v)) : 0;
-      v += 64;
-    }
-  }
-};
-
-// Decode `rate` words into 64 floats (block-local order).
+// Decode the slice `in` (rate words followed by kSlackWords zero words) into
+// 64 floats (block-local order).
 template <int RATE>
 ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt) {
   const int rate = RATE > 0 ? RATE : rate_rt;
-  const int maxbits = 64 * rate;
-  BitReader r;
-  r.init(in, rate);
-  uint64_t head = r.w0;
-  int bits = 0, emax = 0;
+  const uint32_t maxbits = 64u * (uint32_t)rate;
+  uint64_t head = in[0];
+  uint32_t pos = maxbits;  // an empty block decodes to zeros
+  int emax = 0;
   if (head & 1) {
     emax = (int)((head >> 1) & 0xff) - 127;
-    bits = maxbits - 9;
-    r.consume(9);
+    pos = 9;
   }
-  uint32_t pl[64];
+  uint64_t X[32];  // bit planes, then (after the transpose) coefficients s, 32+s
   int n = 0;
 #pragma unroll
   for (int k = 31; k >= 0; k--) {
     uint64_t x = 0;
-    if (bits > 0) {
-      int m = n < bits ? n : bits;
-      x = r.w0 & low_mask(m);
-      r.consume(m);
-      bits -= m;
-      while (n < 64 && bits > 0) {
-        uint64_t win = r.w0;
-        bits -= 1;  // the group test
-        if (!(win & 1)) {
-          r.consume(1);
-          break;
+    if (pos < maxbits) {
+      uint64_t w = window64(in, pos);
+      int m = (int)(maxbits - pos) < n ? (int)(maxbits - pos) : n;
+      x = w & low_mask(m);
+      pos += m;
+      if (n < 64 && pos < maxbits) {
+        int g = (int)((w >> m) & 1);  // first group test (m < 64 here)
+        pos += 1;
+        while (g) {
+          uint64_t s = window64(in, pos);  // the scan
+          int lim = 63 - n;
+          if ((int)(maxbits - pos) < lim) lim = (int)(maxbits - pos);
+          int z = s ? ctz64(s) : 64;
+          int t = z < lim ? z : lim;
+          int found = z < lim;
+          x |= uint64_t(1) << (n + t);
+          n += t + 1;
+          pos += t + found;
+          g = (n < 64 && pos < maxbits) ? (int)((s >> (t + found)) & 1) : 0;
+          pos += n < 64 ? 1 : 0;
         }
-        int lim = 63 - n < bits ? 63 - n : bits;
-        uint64_t s = win >> 1;
-        int z = s ? ctz64(s) : 64;
-        int t = z < lim ? z : lim;
-        int found = z < lim;
-        r.consume(1 + t + found);
-        bits -= t + found;
-        n += t;
-        x |= uint64_t(1) << n;
-        n++;
       }
     }
-    pl[k] = (uint32_t)x;
-    pl[32 + k] = (uint32_t)(x >> 32);
+    X[k] = x;
   }
-  transpose32(pl);
-  transpose32(pl + 32);
+  transpose32x2(X);
   int32_t q[64];
 #pragma unroll
-  for (int s = 0; s < 64; s++)
-    q[kSeq.idx[s]] = (int32_t)((pl[s] ^ kNegabinaryMask) - kNegabinaryMask);
+  for (int s = 0; s < 32; s++) {
+    q[kSeq.idx[s]] = (int32_t)(((uint32_t)X[s] ^ kNegabinaryMask) - kNegabinaryMask);
+    q[kSeq.idx[32 + s]] = (int32_t)(((uint32_t)(X[s] >> 32) ^ kNegabinaryMask) - kNegabinaryMask);
+  }
   xform_inv(q);
   if (emax >= -95) {
     // float(q) is one rounding and the power-of-two scale is exact (normal result)

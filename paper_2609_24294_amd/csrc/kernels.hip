@@ -17,6 +17,8 @@
 
 namespace zfpx {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------------------
 // Block location
 // ---------------------------------------------------------------------------
@@ -85,7 +87,7 @@ __device__ __forceinline__ void gather(const float* __restrict__ src, const Bloc
       int len = v.rlen[dy];
       float* o = val + 16 * dz + 4 * dy;
       if (VEC4 && v.x0 + 3 < len) {
-        float4 f = *reinterpret_cast<const float4*>(src + base + v.x0);
+        f32x4 f = *reinterpret_cast<const f32x4*>(src + base + v.x0);
         o[0] = f.x;
         o[1] = f.y;
         o[2] = f.z;
@@ -115,7 +117,8 @@ __device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView
           int len = v.rlen[dy];
           const float* o = val + 16 * dz + 4 * dy;
           if (VEC4 && v.x0 + 3 < len) {
-            *reinterpret_cast<float4*>(dst + base + v.x0) = make_float4(o[0], o[1], o[2], o[3]);
+            f32x4 f = {o[0], o[1], o[2], o[3]};
+            *reinterpret_cast<f32x4*>(dst + base + v.x0) = f;
           } else {
 #pragma unroll
             for (int dx = 0; dx < 4; dx++)
@@ -127,19 +130,64 @@ __device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView
   }
 }
 
+// Copy a tile's coded words between LDS slices (stride words per block) and
+// global memory (rate words per block, contiguous).  For rates dividing 64,
+// lane l always handles word l % rate of every (64/rate)-th block, so the
+// addresses are a per-lane base plus compile-time offsets.
+template <int RATE, bool TO_GLOBAL>
+__device__ __forceinline__ void copy_tile(uint64_t* __restrict__ g, uint64_t* lds, int lane,
+                                          int nact, int rate_rt) {
+  if constexpr (RATE > 0 && 64 % RATE == 0) {
+    constexpr int stride = (RATE + kSlackWords) | 1;
+    constexpr int step = 64 / RATE;  // blocks per row of 64 words
+    const int b = lane / RATE, idx = lane % RATE;
+    uint64_t* l = lds + b * stride + idx;
+#pragma unroll
+    for (int j = 0; j < RATE; j++) {
+      if (b + j * step < nact) {
+        if (TO_GLOBAL)
+          g[lane + 64 * j] = l[j * step * stride];
+        else
+          l[j * step * stride] = g[lane + 64 * j];
+      }
+    }
+  } else {
+    const int rate = RATE > 0 ? RATE : rate_rt;
+    const int stride = (rate + kSlackWords) | 1;
+    const int nw = nact * rate;
+    for (int w = lane; w < nw; w += 64) {
+      int blk = w / rate;
+      int idx = w - blk * rate;
+      if (TO_GLOBAL)
+        g[w] = lds[blk * stride + idx];
+      else
+        lds[blk * stride + idx] = g[w];
+    }
+  }
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-__host__ __device__ constexpr int lds_stride(int rate) { return rate | 1; }
+// Words per lane slice: the stream plus zero slack, odd to spread LDS banks.
+__host__ __device__ constexpr int lds_stride(int rate) { return (rate + kSlackWords) | 1; }
 
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
 
-template <int RATE, bool VEC4, class Geo>
+// Returns x unchanged but hides its value from the optimiser, so that work
+// derived from it is not hoisted out of the tile loop (which would hold that
+// work in registers for the whole kernel and cut occupancy).
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <int RATE, bool VEC4, bool PERSIST, class Geo>
 __global__ __launch_bounds__(256) void k_encode(Geo geo, const float* __restrict__ src,
                                                 uint64_t* __restrict__ out, int rate_rt,
                                                 int32_t b_begin, int32_t b_end) {
@@ -152,30 +200,32 @@ __global__ __launch_bounds__(256) void k_encode(Geo geo, const float* __restrict
   uint64_t* wlds = lds + (size_t)wave * 64 * stride;
   const int32_t nblk = b_end - b_begin;
   const int32_t ntiles = (nblk + 63) >> 6;
-  for (int32_t t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
+  int32_t t = blockIdx.x * waves + wave;
+  if (!PERSIST && t >= ntiles) return;
+  for (;;) {
+    const int ln = opaque(lane);
     const int32_t b0 = b_begin + (t << 6);
-    const int32_t b = b0 + lane;
+    const int32_t b = b0 + ln;
     const int nact = b_end - b0 < 64 ? b_end - b0 : 64;
-    if (lane < nact) {
+    uint64_t* slice = wlds + ln * stride;
+    for (int i = 0; i < stride; i++) slice[i] = 0;
+    if (ln < nact) {
       BlockView v;
       geo.locate(b, v);
       float val[64];
       gather<VEC4>(src, v, val);
-      encode_block<RATE>(val, wlds + lane * stride, rate);
+      encode_block<RATE>(val, slice, rate);
     }
     wave_sync_lds();
-    uint64_t* o = out + (int64_t)b0 * rate;
-    const int nw = nact * rate;
-    for (int w = lane; w < nw; w += 64) {
-      int blk = w / rate;
-      int idx = w - blk * rate;
-      o[w] = wlds[blk * stride + idx];
-    }
+    copy_tile<RATE, true>(out + (int64_t)b0 * rate, wlds, opaque(lane), nact, rate);
+    if (!PERSIST) break;
     wave_sync_lds();
+    t += gridDim.x * waves;
+    if (t >= ntiles) break;
   }
 }
 
-template <int RATE, bool VEC4, class Geo>
+template <int RATE, bool VEC4, bool PERSIST, class Geo>
 __global__ __launch_bounds__(256) void k_decode(Geo geo, const uint64_t* __restrict__ in,
                                                 float* __restrict__ dst, int rate_rt,
                                                 int32_t b_begin, int32_t b_end) {
@@ -188,26 +238,28 @@ __global__ __launch_bounds__(256) void k_decode(Geo geo, const uint64_t* __restr
   uint64_t* wlds = lds + (size_t)wave * 64 * stride;
   const int32_t nblk = b_end - b_begin;
   const int32_t ntiles = (nblk + 63) >> 6;
-  for (int32_t t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
+  int32_t t = blockIdx.x * waves + wave;
+  if (!PERSIST && t >= ntiles) return;
+  for (;;) {
+    const int ln = opaque(lane);
     const int32_t b0 = b_begin + (t << 6);
-    const int32_t b = b0 + lane;
+    const int32_t b = b0 + ln;
     const int nact = b_end - b0 < 64 ? b_end - b0 : 64;
-    const uint64_t* ip = in + (int64_t)b0 * rate;
-    const int nw = nact * rate;
-    for (int w = lane; w < nw; w += 64) {
-      int blk = w / rate;
-      int idx = w - blk * rate;
-      wlds[blk * stride + idx] = ip[w];
-    }
+    for (int i = rate; i < stride; i++) wlds[ln * stride + i] = 0;  // zero slack
+    copy_tile<RATE, false>(const_cast<uint64_t*>(in) + (int64_t)b0 * rate, wlds, ln, nact,
+                           rate);
     wave_sync_lds();
-    if (lane < nact) {
+    if (ln < nact) {
       float val[64];
-      decode_block<RATE>(wlds + lane * stride, val, rate);
+      decode_block<RATE>(wlds + opaque(lane) * stride, val, rate);
       BlockView v;
       geo.locate(b, v);
       scatter<VEC4>(dst, v, val);
     }
+    if (!PERSIST) break;
     wave_sync_lds();
+    t += gridDim.x * waves;
+    if (t >= ntiles) break;
   }
 }
 
@@ -284,35 +336,45 @@ int device_cu_count() {
   return g_cus;
 }
 
-static dim3 grid_for(int32_t nblocks, LaunchCfg cfg) {
+static dim3 grid_for(int32_t nblocks, LaunchCfg cfg, bool* persistent) {
   int waves = cfg.wg / 64;
   int64_t ntiles = ((int64_t)nblocks + 63) / 64;
   int64_t full = (ntiles + waves - 1) / waves;
-  int64_t g = cfg.grid > 0 && cfg.grid < full ? cfg.grid : full;
+  *persistent = cfg.grid > 0 && cfg.grid < full;
+  int64_t g = *persistent ? cfg.grid : full;
   return dim3((unsigned)(g > 0 ? g : 1));
 }
 
-#define ZFPX_RATE_SWITCH(KERNEL, GEO, VEC4, ...)                                         \
+#define ZFPX_RATE_SWITCH2(KERNEL, GEO, VEC4, PERSIST, ...)                                \
   switch (rate) {                                                                          \
     case 8:                                                                                \
-      hipLaunchKernelGGL((KERNEL<8, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);        \
+      hipLaunchKernelGGL((KERNEL<8, VEC4, PERSIST, GEO>), grid, block, shm, s, __VA_ARGS__); \
       break;                                                                               \
     case 16:                                                                               \
-      hipLaunchKernelGGL((KERNEL<16, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);       \
+      hipLaunchKernelGGL((KERNEL<16, VEC4, PERSIST, GEO>), grid, block, shm, s, __VA_ARGS__); \
       break;                                                                               \
     case 32:                                                                               \
-      hipLaunchKernelGGL((KERNEL<32, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);       \
+      hipLaunchKernelGGL((KERNEL<32, VEC4, PERSIST, GEO>), grid, block, shm, s, __VA_ARGS__); \
       break;                                                                               \
     default:                                                                               \
-      hipLaunchKernelGGL((KERNEL<0, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);        \
+      hipLaunchKernelGGL((KERNEL<0, VEC4, PERSIST, GEO>), grid, block, shm, s, __VA_ARGS__); \
       break;                                                                               \
+  }
+
+// One tile per wavefront unless the configuration asks for a persistent grid.
+#define ZFPX_RATE_SWITCH(KERNEL, GEO, VEC4, ...)                                         \
+  if (persistent) {                                                                        \
+    ZFPX_RATE_SWITCH2(KERNEL, GEO, VEC4, true, __VA_ARGS__)                                \
+  } else {                                                                                 \
+    ZFPX_RATE_SWITCH2(KERNEL, GEO, VEC4, false, __VA_ARGS__)                               \
   }
 
 hipError_t launch_plan_encode(const PlanDev& p, bool vec4, const float* src, uint64_t* out,
                               int rate, int32_t b_begin, int32_t b_end, LaunchCfg cfg,
                               hipStream_t s) {
   if (b_end <= b_begin) return hipSuccess;
-  dim3 grid = grid_for(b_end - b_begin, cfg), block(cfg.wg);
+  bool persistent;
+  dim3 grid = grid_for(b_end - b_begin, cfg, &persistent), block(cfg.wg);
   size_t shm = lds_bytes(cfg.wg, rate);
   PlanGeo geo{p};
   if (vec4) {
@@ -327,7 +389,8 @@ hipError_t launch_plan_decode(const PlanDev& p, bool vec4, const uint64_t* in, f
                               int rate, int32_t b_begin, int32_t b_end, LaunchCfg cfg,
                               hipStream_t s) {
   if (b_end <= b_begin) return hipSuccess;
-  dim3 grid = grid_for(b_end - b_begin, cfg), block(cfg.wg);
+  bool persistent;
+  dim3 grid = grid_for(b_end - b_begin, cfg, &persistent), block(cfg.wg);
   size_t shm = lds_bytes(cfg.wg, rate);
   PlanGeo geo{p};
   if (vec4) {
@@ -342,7 +405,8 @@ hipError_t launch_regular_encode(const RegularDev& g, bool vec4, const float* sr
                                  uint64_t* out, int rate, int32_t nblocks, LaunchCfg cfg,
                                  hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  dim3 grid = grid_for(nblocks, cfg), block(cfg.wg);
+  bool persistent;
+  dim3 grid = grid_for(nblocks, cfg, &persistent), block(cfg.wg);
   size_t shm = lds_bytes(cfg.wg, rate);
   RegularGeo geo{g};
   int32_t b0 = 0;
@@ -357,7 +421,8 @@ hipError_t launch_regular_encode(const RegularDev& g, bool vec4, const float* sr
 hipError_t launch_regular_decode(const RegularDev& g, bool vec4, const uint64_t* in, float* dst,
                                  int rate, int32_t nblocks, LaunchCfg cfg, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  dim3 grid = grid_for(nblocks, cfg), block(cfg.wg);
+  bool persistent;
+  dim3 grid = grid_for(nblocks, cfg, &persistent), block(cfg.wg);
   size_t shm = lds_bytes(cfg.wg, rate);
   RegularGeo geo{g};
   int32_t b0 = 0;
