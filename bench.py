@@ -44,7 +44,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip rate-8 and f16 legs")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (for counter calibration)")
+                    help="also run a plain 256 MiB device copy (for counter calibration)")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the error report")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the batched vs per-chunk comparison (lambda->theta buffer)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
+    ap.add_argument("--serving-requests", type=int, default=10000)
     return ap.parse_args()
 
 
@@ -148,13 +153,27 @@ def main():
         del h
 
     if args.copy_calibration:
-        log("plain 1 GiB device copy (counter calibration)")
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        log("plain 256 MiB device copy (counter calibration)")
+        a = torch.empty(1 << 26, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
+        b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    accuracy = None
+    if not args.no_accuracy:
+        accuracy = accuracy_report(plan, src[0], dst[0], nvals, nblocks, torch, zfpx, W)
+
+    batching = None
+    if not args.no_batching:
+        del src, dst, send
+        torch.cuda.empty_cache()
+        batching = batching_report(torch, zfpx, W)
+
+    serving = None
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        serving = serving_report(torch, zfpx, W, args.serving_requests)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -187,8 +206,179 @@ def main():
                      "algorithmic_bytes": alg_dom, "traffic": None},
         "cpu_baseline": cpu,
         **extras,
+        "accuracy": accuracy,
+        "batching": batching,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def accuracy_report(plan, src, dst, nvals, nblocks, torch, zfpx, W):
+    """Relative error of each rate and of float16 against the FP64 copy of the
+    synthetic fields (untimed), plus the bytes reduction of the buffer."""
+    import numpy as np
+
+    from paper_2609_24294_amd import metrics
+    log("accuracy: error of rates 8/16/32 and float16 against the FP64 fields")
+    _, x64 = W.zlambda_fields(want_f64=True)
+    names = ("u", "v", "T", "q")
+    out = {"reference": "FP64 copy of the synthetic fields; per-block L2 relative error over "
+                        "4x4x4 blocks (mean/max), global L2 error, pointwise for T and q"}
+    shape = x64.shape
+    for r in (8, 16, 32):
+        send = torch.empty(nblocks * r, dtype=torch.int64, device=src.device)
+        zfpx.zfpx_pack_encode(plan, src, r, send)
+        zfpx.zfpx_decode_unpack(plan, send, r, dst)
+        back = dst.cpu().numpy().reshape(shape)
+        out[f"rate{r}"] = {
+            "bytes_reduction": round(metrics.bytes_reduction(nvals, nblocks * 8 * r), 3),
+            **{names[f]: {k: float(f"{v:.3e}") for k, v in
+                          metrics.error_report(x64[f], back[f], pointwise=f in (2, 3)).items()}
+               for f in range(4)}}
+        del send
+    h = zfpx.f16_truncate(src)
+    back = zfpx.f16_restore(h).cpu().numpy().reshape(shape)
+    out["f16"] = {"bytes_reduction": 2.0,
+                  **{names[f]: {k: float(f"{v:.3e}") for k, v in
+                                metrics.error_report(x64[f], back[f], pointwise=f in (2, 3)).items()}
+                     for f in range(4)}}
+    x32 = src.cpu().numpy().reshape(shape)
+    out["float32_storage"] = {names[f]: float(f"{metrics.error_report(x64[f], x32[f], False)['block_mean']:.3e}")
+                              for f in range(4)}
+    return out
+
+
+def batching_report(torch, zfpx, W, rate=16, reps=10):
+    """The lambda->theta buffer (O1280 x 137 levels, 256 uneven chunks): one
+    autotuned launch per op, the two captured in a HIP graph, against one
+    launch per chunk of the same kernels."""
+    import ctypes
+
+    log("batching: generating the lambda->theta buffer (O1280 x 137 levels)")
+    x = W.ltheta_field()
+    cs = W.ltheta_chunkset()
+    plan = zfpx.Plan.from_chunkset(cs)
+    dev = torch.device("cuda:0")
+    src = torch.from_numpy(x.reshape(-1)).to(dev)
+    del x
+    send = torch.empty(plan.nblocks * rate, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    tuned = {}
+    for op in (zfpx.OP_ENCODE, zfpx.OP_DECODE):
+        us = zfpx.zfpx_autotune(plan, op, rate, src, send, dst)
+        tuned["encode" if op == 0 else "decode"] = {
+            "config": dict(zip(("wg", "grid"), zfpx.zfpx_plan_get_config(plan, op, rate))),
+            "us": round(us, 1)}
+    g = zfpx.Graph(plan, rate, src, send, dst)
+    L = zfpx.library()
+    h, s_ = plan.handle, stream.cuda_stream
+    sp, sn, dp, dn = src.data_ptr(), src.numel(), dst.data_ptr(), dst.numel()
+    wp, wn = send.data_ptr(), send.numel() * 8
+
+    def direct():
+        L.zfpx_pack_encode(h, sp, sn, rate, wp, wn, s_)
+        L.zfpx_decode_unpack(h, wp, wn, rate, dp, dn, s_)
+
+    def per_chunk():
+        for c in range(cs.nchunks):
+            L.zfpx_pack_encode_chunks(h, c, 1, sp, sn, rate, wp, wn, s_)
+        for c in range(cs.nchunks):
+            L.zfpx_decode_unpack_chunks(h, c, 1, wp, wn, rate, dp, dn, s_)
+
+    def timeit(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps * 1e3
+        return round(e0.elapsed_time(e1) / reps, 4), round(wall, 4)
+
+    log("batching: timing graph, direct and per-chunk forms")
+    gpu_g, wall_g = timeit(lambda: g.launch(stream))
+    gpu_d, wall_d = timeit(direct)
+    gpu_c, wall_c = timeit(per_chunk)
+    nvals = plan.nvalues
+    g.close()
+    return {"workload": "lambda->theta buffer, O1280 (2560 rows) x 137 levels f32 (3.617 GB), "
+                        "256 chunks of 8 or 12 rows", "rate": rate, "values": nvals,
+            "graph_ms": gpu_g, "direct_ms": gpu_d, "per_chunk_ms": gpu_c,
+            "wall_ms": {"graph": wall_g, "direct": wall_d, "per_chunk": wall_c},
+            "speedup_graph_vs_per_chunk": round(gpu_c / gpu_g, 3),
+            "graph_gbs_fp32_input": round(4 * nvals / (gpu_g * 1e-3) / 1e9, 1),
+            "tuned": tuned}
+
+
+def serving_report(torch, zfpx, W, count):
+    """Poisson arrivals of mixed compress/decompress requests (64 KB .. 64 MB of
+    float32, rate 8/16/32) at 25/50/75/90% of the saturated throughput; p50 and
+    p99 latency of the serving loop against one launch per request."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    log("serving: request pool and buffers")
+    nx_max = 32768
+    pool = torch.from_numpy(W.serving_pool(nx_max=nx_max)).to(dev)
+    coded = {r: zfpx.zfpx_encode_fixed_rate(pool, r) for r in (8, 16, 32)}
+    nsets = 32
+    words_out = [torch.empty(nx_max // 4 * 16 * 2 * 32, dtype=torch.int64, device=dev)
+                 for _ in range(nsets)]
+    float_out = [torch.empty_like(pool) for _ in range(nsets)]
+
+    def build(stream):
+        reqs, nbytes = [], []
+        for i, q in enumerate(stream):
+            k = i % nsets
+            if q.op == 0:
+                view = pool[:, :, : q.nx]
+                rq = zfpx.make_request(0, q.rate, view, words_out[k])
+            else:
+                view = float_out[k][:, :, : q.nx]
+                rq = zfpx.make_request(1, q.rate, view, coded[q.rate])
+            reqs.append(rq)
+            nbytes.append(4 * 8 * 64 * q.nx)
+        return reqs, np.array(nbytes, np.float64)
+
+    base = W.request_stream(count, 1.0)
+    reqs, nbytes = build(base)
+    zero = np.zeros(count)
+    log(f"serving: saturated throughput ({count} requests at once, one launch each)")
+    lat = zfpx.zfpx_plain_replay(reqs, zero, timeout_s=300.0)
+    sat = nbytes.sum() / lat.max()
+    mean_bytes = nbytes.mean()
+    out = {"requests_per_point": count, "budget_bytes": 64 << 30,
+           "saturated_gbs_fp32": round(sat / 1e9, 1), "mean_request_mb": round(mean_bytes / 1e6, 2),
+           "note": "request buffers are drawn from 32 rotating sets; latency = completion seen "
+                   "by the host minus scheduled arrival", "points": []}
+    for load in (0.25, 0.5, 0.75, 0.9):
+        gap = mean_bytes / (load * sat)
+        stream = W.request_stream(count, gap)
+        arrival = np.array([q.t_arrive for q in stream])
+        reqs, nbytes = build(stream)
+        log(f"serving: load {load:.2f}, mean gap {gap * 1e6:.1f} us")
+        sv = zfpx.Server(64 << 30, max_slots=1024)
+        ls = sv.replay(reqs, arrival, timeout_s=300.0)
+        sv.close()
+        lp = zfpx.zfpx_plain_replay(reqs, arrival, timeout_s=300.0)
+        span_s = (arrival + ls).max()
+        span_p = (arrival + lp).max()
+        out["points"].append({
+            "load": load, "mean_gap_us": round(gap * 1e6, 2),
+            "server": {"p50_us": round(float(np.percentile(ls, 50)) * 1e6, 1),
+                       "p99_us": round(float(np.percentile(ls, 99)) * 1e6, 1),
+                       "gbs_fp32": round(nbytes.sum() / span_s / 1e9, 1)},
+            "per_request_launch": {"p50_us": round(float(np.percentile(lp, 50)) * 1e6, 1),
+                                   "p99_us": round(float(np.percentile(lp, 99)) * 1e6, 1),
+                                   "gbs_fp32": round(nbytes.sum() / span_p / 1e9, 1)}})
+    torch.cuda.synchronize()
+    return out
 
 
 def cpu_baseline(cs, rate):

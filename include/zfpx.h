@@ -229,6 +229,73 @@ int zfpx_graph_launch(zfpx_graph* graph, void* stream);
 int zfpx_graph_destroy(zfpx_graph* graph);
 
 /* -------------------------------------------------------------------------
+ * Serving: continuous batching of compress / decompress requests
+ * ---------------------------------------------------------------------- */
+
+/*
+ * A request codes one regular float32 array (as zfpx_encode_fixed_rate /
+ * zfpx_decode_fixed_rate): op 0 compresses d_in (float32, strides sx,sy,sz)
+ * into d_out (coded words, 8-byte aligned); op 1 decompresses d_in (words)
+ * into d_out (float32).  Buffers are caller-owned device memory that must stay
+ * valid until the request completes.  tag is free for the caller.
+ *
+ * The server realises the paper's point that fixed-rate ZFP needs no
+ * coordination between blocks (Section II-C) as a service: requests are
+ * admitted in arrival order while a ring slot is free and their input +
+ * output bytes fit in `hbm_budget_bytes`; admitted requests are cut into
+ * 64-block tiles that a device-resident loop (a persistent kernel on a
+ * private stream) interleaves with the tiles of every other request in
+ * flight.  Results are bit-identical to the one-request launch form.
+ *
+ *   zfpx_server_create : max_slots ring entries (1..65536); workgroups of the
+ *                        device loop (0 = 4 per compute unit).  Allocates
+ *                        pinned host memory and device memory.
+ *   zfpx_server_submit : queue a request; EINVAL if malformed or larger than
+ *                        the whole budget, EAGAIN if the queue is full.
+ *                        Thread-safe.  Returns a ticket.
+ *   zfpx_server_progress / _poll : collect completions and admit more;
+ *                        poll reports done and the latency (seconds from
+ *                        submit to the host seeing completion) and forgets
+ *                        the ticket once done.
+ *   zfpx_server_drain  : progress until nothing is queued or in flight
+ *                        (EAGAIN after timeout_s).
+ *   zfpx_server_stats  : requests admitted, largest in-flight byte total seen,
+ *                        device-loop launches.
+ *   zfpx_server_destroy: stop the device loop, wait for it, free.
+ *   zfpx_server_replay : replay a request trace (arrival times in seconds
+ *                        from the start, non-decreasing) through the server
+ *                        and write each request's latency (completion minus
+ *                        scheduled arrival).
+ *   zfpx_plain_replay  : the same trace with one launch per request, in
+ *                        arrival order on one stream (the plain form).
+ */
+typedef struct {
+  int32_t op;
+  int32_t rate;
+  int64_t nx, ny, nz;
+  int64_t sx, sy, sz;
+  const void* d_in;
+  void* d_out;
+  uint64_t tag;
+} zfpx_request;
+
+typedef struct zfpx_server zfpx_server;
+
+int zfpx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t workgroups,
+                       zfpx_server** out);
+int zfpx_server_submit(zfpx_server* sv, const zfpx_request* rq, uint64_t* ticket);
+int zfpx_server_progress(zfpx_server* sv);
+int zfpx_server_poll(zfpx_server* sv, uint64_t ticket, int* done, double* latency_s);
+int zfpx_server_drain(zfpx_server* sv, double timeout_s);
+int zfpx_server_stats(zfpx_server* sv, uint64_t* admitted, size_t* max_inflight_bytes,
+                      uint64_t* loop_launches);
+int zfpx_server_destroy(zfpx_server* sv);
+int zfpx_server_replay(zfpx_server* sv, const zfpx_request* rq, const double* arrival_s,
+                       int64_t n, double timeout_s, double* latency_s);
+int zfpx_plain_replay(const zfpx_request* rq, const double* arrival_s, int64_t n,
+                      double timeout_s, void* stream, double* latency_s);
+
+/* -------------------------------------------------------------------------
  * float16 comparator
  * ---------------------------------------------------------------------- */
 

@@ -59,6 +59,42 @@ hipError_t launch_regular_decode(const RegularDev& g, bool vec4, const uint64_t*
 hipError_t launch_f16_truncate(const float* in, size_t n, uint16_t* out, hipStream_t s);
 hipError_t launch_f16_restore(const uint16_t* in, size_t n, float* out, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Serving: a request ring shared by the host (writer) and a persistent
+// device loop (reader).
+// ---------------------------------------------------------------------------
+struct ServeDesc {   // one admitted request; host-coherent memory, slot = seq % cap
+  uint64_t seq;      // request number
+  int32_t op;        // 0 = encode (float32 -> words), 1 = decode
+  int32_t rate;
+  int32_t nblocks, ntiles;
+  int32_t vec4, pad;
+  RegularDev geo;
+  uint64_t in, out;  // device addresses
+};
+
+struct ServeCtl {        // host-coherent control block
+  uint64_t published;    // requests 0 .. published-1 are in the ring
+  uint64_t oldest;       // no request older than this has work left (a hint)
+  uint32_t stop;         // set by the host to end the device loop
+  uint32_t pad;
+};
+
+struct ServeDev {        // arguments of the device loop
+  ServeCtl* ctl;         // device view of the control block
+  const ServeDesc* ring; // device view of the ring (cap entries)
+  uint64_t* done_flag;   // host-coherent, per slot: seq + 1 once complete
+  uint64_t* claim;       // device memory, per slot: (seq << 32) | tiles claimed
+  uint64_t* done;        // device memory, per slot: (seq << 32) | tiles done
+  int32_t cap;
+  int32_t pad;
+  uint64_t idle_ticks;   // leave after this long without work (real-time ticks)
+  uint64_t max_ticks;    // and in any case after this long
+};
+
+hipError_t launch_serve(const ServeDev& d, int workgroups, hipStream_t s);
+constexpr int kServeWaves = 2;  // wavefronts per workgroup of the device loop
+
 // LDS bytes a workgroup of `wg` threads needs at `rate`.
 size_t lds_bytes(int wg, int rate);
 // Largest LDS per workgroup of the current device (cached).

@@ -187,41 +187,67 @@ __device__ __forceinline__ int opaque(int x) {
   return x;
 }
 
+// One 64-block tile: gather + encode into the lane slices, then copy the
+// tile's words out (encode), or copy in + decode + scatter (decode).
+template <int RATE, bool VEC4, class Geo>
+__device__ __forceinline__ void encode_tile(const Geo& geo, const float* __restrict__ src,
+                                            uint64_t* __restrict__ out, int rate, int lane,
+                                            uint64_t* wlds, int32_t b0, int nact) {
+  const int stride = lds_stride(RATE > 0 ? RATE : rate);
+  uint64_t* slice = wlds + lane * stride;
+  for (int i = 0; i < stride; i++) slice[i] = 0;
+  if (lane < nact) {
+    BlockView v;
+    geo.locate(b0 + lane, v);
+    float val[64];
+    gather<VEC4>(src, v, val);
+    encode_block<RATE>(val, slice, rate);
+  }
+  wave_sync_lds();
+  copy_tile<RATE, true>(out + (int64_t)b0 * rate, wlds, opaque(lane), nact, rate);
+}
+
+template <int RATE, bool VEC4, class Geo>
+__device__ __forceinline__ void decode_tile(const Geo& geo, const uint64_t* __restrict__ in,
+                                            float* __restrict__ dst, int rate, int lane,
+                                            uint64_t* wlds, int32_t b0, int nact) {
+  const int stride = lds_stride(RATE > 0 ? RATE : rate);
+  for (int i = (RATE > 0 ? RATE : rate); i < stride; i++) wlds[lane * stride + i] = 0;
+  copy_tile<RATE, false>(const_cast<uint64_t*>(in) + (int64_t)b0 * rate, wlds, lane, nact,
+                         rate);
+  wave_sync_lds();
+  if (lane < nact) {
+    float val[64];
+    decode_block<RATE>(wlds + opaque(lane) * stride, val, rate);
+    BlockView v;
+    geo.locate(b0 + lane, v);
+    scatter<VEC4>(dst, v, val);
+  }
+}
+
+// Workgroups cover the tiles of blocks [b_begin, b_end): one tile per
+// wavefront, or (PERSIST) a grid-stride loop over tiles.
 template <int RATE, bool VEC4, bool PERSIST, class Geo>
 __global__ __launch_bounds__(256) void k_encode(Geo geo, const float* __restrict__ src,
                                                 uint64_t* __restrict__ out, int rate_rt,
                                                 int32_t b_begin, int32_t b_end) {
   extern __shared__ uint64_t lds[];
   const int rate = RATE > 0 ? RATE : rate_rt;
-  const int stride = lds_stride(rate);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int waves = blockDim.x >> 6;
-  uint64_t* wlds = lds + (size_t)wave * 64 * stride;
-  const int32_t nblk = b_end - b_begin;
-  const int32_t ntiles = (nblk + 63) >> 6;
+  uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(rate);
+  const int32_t ntiles = (b_end - b_begin + 63) >> 6;
   int32_t t = blockIdx.x * waves + wave;
-  if (!PERSIST && t >= ntiles) return;
+  if (t >= ntiles) return;
   for (;;) {
-    const int ln = opaque(lane);
     const int32_t b0 = b_begin + (t << 6);
-    const int32_t b = b0 + ln;
     const int nact = b_end - b0 < 64 ? b_end - b0 : 64;
-    uint64_t* slice = wlds + ln * stride;
-    for (int i = 0; i < stride; i++) slice[i] = 0;
-    if (ln < nact) {
-      BlockView v;
-      geo.locate(b, v);
-      float val[64];
-      gather<VEC4>(src, v, val);
-      encode_block<RATE>(val, slice, rate);
-    }
-    wave_sync_lds();
-    copy_tile<RATE, true>(out + (int64_t)b0 * rate, wlds, opaque(lane), nact, rate);
+    encode_tile<RATE, VEC4>(geo, src, out, rate, opaque(lane), wlds, b0, nact);
     if (!PERSIST) break;
-    wave_sync_lds();
     t += gridDim.x * waves;
     if (t >= ntiles) break;
+    wave_sync_lds();
   }
 }
 
@@ -231,35 +257,174 @@ __global__ __launch_bounds__(256) void k_decode(Geo geo, const uint64_t* __restr
                                                 int32_t b_begin, int32_t b_end) {
   extern __shared__ uint64_t lds[];
   const int rate = RATE > 0 ? RATE : rate_rt;
-  const int stride = lds_stride(rate);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int waves = blockDim.x >> 6;
-  uint64_t* wlds = lds + (size_t)wave * 64 * stride;
-  const int32_t nblk = b_end - b_begin;
-  const int32_t ntiles = (nblk + 63) >> 6;
+  uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(rate);
+  const int32_t ntiles = (b_end - b_begin + 63) >> 6;
   int32_t t = blockIdx.x * waves + wave;
-  if (!PERSIST && t >= ntiles) return;
+  if (t >= ntiles) return;
   for (;;) {
-    const int ln = opaque(lane);
     const int32_t b0 = b_begin + (t << 6);
-    const int32_t b = b0 + ln;
     const int nact = b_end - b0 < 64 ? b_end - b0 : 64;
-    for (int i = rate; i < stride; i++) wlds[ln * stride + i] = 0;  // zero slack
-    copy_tile<RATE, false>(const_cast<uint64_t*>(in) + (int64_t)b0 * rate, wlds, ln, nact,
-                           rate);
-    wave_sync_lds();
-    if (ln < nact) {
-      float val[64];
-      decode_block<RATE>(wlds + opaque(lane) * stride, val, rate);
-      BlockView v;
-      geo.locate(b, v);
-      scatter<VEC4>(dst, v, val);
-    }
+    decode_tile<RATE, VEC4>(geo, in, dst, rate, opaque(lane), wlds, b0, nact);
     if (!PERSIST) break;
-    wave_sync_lds();
     t += gridDim.x * waves;
     if (t >= ntiles) break;
+    wave_sync_lds();
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Serving loop
+// ---------------------------------------------------------------------------
+// Every wavefront is an independent worker.  It walks the request ring in
+// order (cursor = request number), claims 64-block tiles of the request at
+// its cursor with a compare-and-swap on a per-slot counter tagged with the
+// request number (so that a slot reused for a later request is never
+// confused with the earlier one), codes the tile, and counts it done; the
+// wavefront that completes a request's last tile raises the request's
+// completion flag in host memory.  Requests therefore overlap on the device
+// as soon as they are published.  Every wavefront leaves when the host sets
+// the stop flag, after `idle_ticks` without work, or after `max_ticks` in
+// total, so the grid always drains.
+
+__device__ __forceinline__ uint64_t sys_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t sys_load32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint64_t relaxed_sys_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ int64_t relaxed_sys_load_i(const int64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ int32_t relaxed_sys_load_i32(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ void serve_tile(const ServeDesc& q, int lane, uint64_t* wlds,
+                                           int32_t tile) {
+  RegularGeo geo{q.geo};
+  const int32_t b0 = tile << 6;
+  const int nact = q.nblocks - b0 < 64 ? q.nblocks - b0 : 64;
+  if (q.op == 0) {
+    const float* src = reinterpret_cast<const float*>(q.in);
+    uint64_t* out = reinterpret_cast<uint64_t*>(q.out);
+    if (q.vec4 && q.rate == 8)
+      encode_tile<8, true>(geo, src, out, 8, lane, wlds, b0, nact);
+    else if (q.vec4 && q.rate == 16)
+      encode_tile<16, true>(geo, src, out, 16, lane, wlds, b0, nact);
+    else if (q.vec4 && q.rate == 32)
+      encode_tile<32, true>(geo, src, out, 32, lane, wlds, b0, nact);
+    else
+      encode_tile<0, false>(geo, src, out, q.rate, lane, wlds, b0, nact);
+  } else {
+    const uint64_t* in = reinterpret_cast<const uint64_t*>(q.in);
+    float* dst = reinterpret_cast<float*>(q.out);
+    if (q.vec4 && q.rate == 8)
+      decode_tile<8, true>(geo, in, dst, 8, lane, wlds, b0, nact);
+    else if (q.vec4 && q.rate == 16)
+      decode_tile<16, true>(geo, in, dst, 16, lane, wlds, b0, nact);
+    else if (q.vec4 && q.rate == 32)
+      decode_tile<32, true>(geo, in, dst, 32, lane, wlds, b0, nact);
+    else
+      decode_tile<0, false>(geo, in, dst, q.rate, lane, wlds, b0, nact);
+  }
+}
+
+__global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
+  extern __shared__ uint64_t lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(32);
+  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+  uint64_t t_work = t_start;
+  uint64_t cursor = sys_load(&d.ctl->oldest);
+  uint64_t have = ~uint64_t(0);  // request whose descriptor is in q
+  ServeDesc q{};
+  for (;;) {
+    const uint64_t now = __builtin_amdgcn_s_memrealtime();
+    if (now - t_start > d.max_ticks) break;
+    const uint64_t pub = sys_load(&d.ctl->published);
+    if (cursor >= pub) {
+      if (sys_load32(&d.ctl->stop) || now - t_work > d.idle_ticks) break;
+      __builtin_amdgcn_s_sleep(4);
+      continue;
+    }
+    const int slot = (int)(cursor % (uint64_t)d.cap);
+    if (have != cursor) {
+      const ServeDesc* r = d.ring + slot;
+      q.seq = relaxed_sys_load(&r->seq);
+      if (q.seq != cursor) {  // the slot already holds a later request
+        cursor++;
+        continue;
+      }
+      q.op = relaxed_sys_load_i32(&r->op);
+      q.rate = relaxed_sys_load_i32(&r->rate);
+      q.nblocks = relaxed_sys_load_i32(&r->nblocks);
+      q.ntiles = relaxed_sys_load_i32(&r->ntiles);
+      q.vec4 = relaxed_sys_load_i32(&r->vec4);
+      q.geo.nx = relaxed_sys_load_i(&r->geo.nx);
+      q.geo.ny = relaxed_sys_load_i(&r->geo.ny);
+      q.geo.nz = relaxed_sys_load_i(&r->geo.nz);
+      q.geo.sx = relaxed_sys_load_i(&r->geo.sx);
+      q.geo.sy = relaxed_sys_load_i(&r->geo.sy);
+      q.geo.sz = relaxed_sys_load_i(&r->geo.sz);
+      q.geo.nbx = relaxed_sys_load_i32(&r->geo.nbx);
+      q.geo.nby = relaxed_sys_load_i32(&r->geo.nby);
+      q.in = relaxed_sys_load(&r->in);
+      q.out = relaxed_sys_load(&r->out);
+      have = cursor;
+    }
+    // claim a tile (lane 0), then share the result with the wavefront
+    int32_t tile = -1;
+    if (lane == 0) {
+      const uint32_t want = (uint32_t)cursor;
+      for (;;) {
+        uint64_t c = __hip_atomic_load(d.claim + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t cseq = (uint32_t)(c >> 32), cnt = (uint32_t)c;
+        if (cseq != want) {
+          if ((int32_t)(cseq - want) > 0) break;  // slot reused: this request is done
+          // first visitor of this request: reset the done counter, then the claim counter
+          uint64_t dv = __hip_atomic_load(d.done + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if ((uint32_t)(dv >> 32) != want)
+            __hip_atomic_compare_exchange_strong(d.done + slot, &dv, (uint64_t)want << 32,
+                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_compare_exchange_strong(d.claim + slot, &c, (uint64_t)want << 32,
+                                               __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+          continue;
+        }
+        if ((int32_t)cnt >= q.ntiles) break;  // every tile already claimed
+        if (__hip_atomic_compare_exchange_strong(d.claim + slot, &c, c + 1, __ATOMIC_ACQ_REL,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          tile = (int32_t)cnt;
+          break;
+        }
+      }
+    }
+    tile = __shfl(tile, 0, 64);
+    if (tile < 0) {
+      cursor++;
+      continue;
+    }
+    serve_tile(q, opaque(lane), wlds, tile);
+    wave_sync_lds();
+    // make the tile's output visible before counting it done
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    if (lane == 0) {
+      uint64_t prev = __hip_atomic_fetch_add(d.done + slot, 1, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_SYSTEM);
+      if ((int32_t)(uint32_t)prev + 1 == q.ntiles)
+        __hip_atomic_store(d.done_flag + slot, cursor + 1, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    t_work = __builtin_amdgcn_s_memrealtime();
   }
 }
 
@@ -440,6 +605,13 @@ static unsigned elementwise_grid(size_t work) {
   size_t cap = (size_t)g_cus * 16;
   if (g > cap) g = cap;
   return (unsigned)(g > 0 ? g : 1);
+}
+
+hipError_t launch_serve(const ServeDev& d, int workgroups, hipStream_t s) {
+  size_t shm = (size_t)kServeWaves * 64 * lds_stride(32) * sizeof(uint64_t);
+  hipLaunchKernelGGL(k_serve, dim3(workgroups > 0 ? workgroups : 1), dim3(64 * kServeWaves), shm,
+                     s, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_f16_truncate(const float* in, size_t n, uint16_t* out, hipStream_t s) {

@@ -55,6 +55,16 @@ _SIGS = {
     "zfpx_graph_create": (_INT, [_P, _INT, _P, _I64, _P, _SZ, _P, _I64, _c.POINTER(_P)]),
     "zfpx_graph_launch": (_INT, [_P, _P]),
     "zfpx_graph_destroy": (_INT, [_P]),
+    "zfpx_server_create": (_INT, [_SZ, _I32, _I32, _c.POINTER(_P)]),
+    "zfpx_server_submit": (_INT, [_P, _P, _c.POINTER(_c.c_uint64)]),
+    "zfpx_server_progress": (_INT, [_P]),
+    "zfpx_server_poll": (_INT, [_P, _c.c_uint64, _c.POINTER(_INT), _c.POINTER(_c.c_double)]),
+    "zfpx_server_drain": (_INT, [_P, _c.c_double]),
+    "zfpx_server_stats": (_INT, [_P, _c.POINTER(_c.c_uint64), _c.POINTER(_SZ),
+                                 _c.POINTER(_c.c_uint64)]),
+    "zfpx_server_destroy": (_INT, [_P]),
+    "zfpx_server_replay": (_INT, [_P, _P, _P, _I64, _c.c_double, _P]),
+    "zfpx_plain_replay": (_INT, [_P, _P, _I64, _c.c_double, _P, _P]),
     "f16_truncate": (_INT, [_P, _SZ, _P, _P]),
     "f16_restore": (_INT, [_P, _SZ, _P, _P]),
 }
@@ -300,6 +310,89 @@ class Graph:
 
 def zfpx_graph_create(plan, rate, src, send, dst) -> Graph:
     return Graph(plan, rate, src, send, dst)
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+
+class zfpx_request(_c.Structure):
+    _fields_ = [("op", _c.c_int32), ("rate", _c.c_int32),
+                ("nx", _c.c_int64), ("ny", _c.c_int64), ("nz", _c.c_int64),
+                ("sx", _c.c_int64), ("sy", _c.c_int64), ("sz", _c.c_int64),
+                ("d_in", _c.c_void_p), ("d_out", _c.c_void_p), ("tag", _c.c_uint64)]
+
+
+def make_request(op: int, rate: int, array: torch.Tensor, words: torch.Tensor,
+                 tag: int = 0) -> zfpx_request:
+    """A request on a (nz, ny, nx) float32 view `array` and its coded `words`:
+    op 0 encodes array -> words, op 1 decodes words -> array."""
+    nz, ny, nx = array.shape
+    sz, sy, sx = array.stride()
+    fin, fout = (array, words) if op == 0 else (words, array)
+    return zfpx_request(op, rate, nx, ny, nz, sx, sy, sz, _dev(fin), _dev(fout), tag)
+
+
+class Server:
+    """Continuous-batching server around the device-resident loop."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, workgroups: int = 0):
+        h = _P()
+        _check(_lib.zfpx_server_create(hbm_budget_bytes, max_slots, workgroups, _c.byref(h)),
+               "zfpx_server_create")
+        self._h = h
+
+    def submit(self, rq: zfpx_request) -> int:
+        t = _c.c_uint64()
+        _check(_lib.zfpx_server_submit(self._h, _c.byref(rq), _c.byref(t)), "zfpx_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        done, lat = _INT(), _c.c_double()
+        _check(_lib.zfpx_server_poll(self._h, ticket, _c.byref(done), _c.byref(lat)),
+               "zfpx_server_poll")
+        return bool(done.value), lat.value
+
+    def drain(self, timeout_s: float = 60.0) -> None:
+        _check(_lib.zfpx_server_drain(self._h, timeout_s), "zfpx_server_drain")
+
+    def stats(self):
+        a, m, l = _c.c_uint64(), _SZ(), _c.c_uint64()
+        _check(_lib.zfpx_server_stats(self._h, _c.byref(a), _c.byref(m), _c.byref(l)),
+               "zfpx_server_stats")
+        return {"admitted": a.value, "max_inflight_bytes": m.value, "loop_launches": l.value}
+
+    def replay(self, requests, arrival_s, timeout_s: float = 120.0):
+        import numpy as np
+        n = len(requests)
+        arr = (zfpx_request * n)(*requests)
+        t = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        lat = np.zeros(n, np.float64)
+        _check(_lib.zfpx_server_replay(self._h, _c.cast(arr, _P), t.ctypes.data, n, timeout_s,
+                                       lat.ctypes.data), "zfpx_server_replay")
+        return lat
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.zfpx_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def zfpx_plain_replay(requests, arrival_s, timeout_s: float = 120.0, stream=None):
+    import numpy as np
+    n = len(requests)
+    arr = (zfpx_request * n)(*requests)
+    t = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    lat = np.zeros(n, np.float64)
+    _check(_lib.zfpx_plain_replay(_c.cast(arr, _P), t.ctypes.data, n, timeout_s,
+                                  _stream(stream), lat.ctypes.data), "zfpx_plain_replay")
+    return lat
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,123 @@
+"""Serving loop: every result in the mix equals the request run alone
+(tolerance 0), admission respects the HBM budget, errors are reported."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_24294_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _requests(zfpx, pool, rng, count):
+    """Mixed encode/decode requests on views of `pool`, each with its own
+    output buffer, plus the expected outputs computed one launch at a time."""
+    reqs, outs, refs = [], [], []
+    for i in range(count):
+        op = int(rng.integers(0, 2))
+        rate = int(rng.choice([1, 7, 8, 16, 32]))
+        nx = int(rng.choice([4, 12, 64, 300, 1028, 4096]))
+        view = pool[:, :, :nx]
+        if i % 7 == 3:  # a strided view takes the generic path
+            view = pool[:, ::2, : 2 * nx : 2]
+        nbytes = zfpx.zfpx_fixed_rate_bytes(view.shape[2], view.shape[1], view.shape[0], rate)
+        if op == 0:
+            words = torch.zeros(nbytes // 8, dtype=torch.int64, device=DEV)
+            ref = zfpx.zfpx_encode_fixed_rate(view, rate)
+            reqs.append(zfpx.make_request(0, rate, view, words, tag=i))
+            outs.append(words)
+        else:
+            src_words = zfpx.zfpx_encode_fixed_rate(view, rate)
+            arr = torch.full(view.shape, -7.0, device=DEV)
+            ref = torch.full(view.shape, -7.0, device=DEV)
+            zfpx.zfpx_decode_fixed_rate(src_words, rate, ref)
+            reqs.append(zfpx.make_request(1, rate, arr, src_words, tag=i))
+            outs.append((arr, src_words))
+        refs.append(ref)
+    torch.cuda.synchronize()
+    return reqs, outs, refs
+
+
+def _check(outs, refs):
+    for i, (o, r) in enumerate(zip(outs, refs)):
+        got = o if isinstance(o, torch.Tensor) else o[0]
+        assert torch.equal(got, r), f"request {i} differs from its one-launch result"
+
+
+def test_server_mix_equals_alone(zfpx_lib):
+    rng = np.random.default_rng(40)
+    pool = torch.from_numpy(W.serving_pool(nx_max=8192)).to(DEV)
+    reqs, outs, refs = _requests(zfpx_lib, pool, rng, 60)
+    sv = zfpx_lib.Server(64 << 30, max_slots=16)
+    tickets = []
+    for i, rq in enumerate(reqs):
+        tickets.append(sv.submit(rq))
+        if i % 10 == 9:
+            time.sleep(0.002)  # some requests arrive while others run
+    sv.drain(60.0)
+    for t in tickets:
+        done, lat = sv.poll(t)
+        assert done and lat > 0
+    st = sv.stats()
+    sv.close()
+    torch.cuda.synchronize()
+    assert st["admitted"] == len(reqs)
+    _check(outs, refs)
+
+
+def test_server_budget_admission(zfpx_lib):
+    rng = np.random.default_rng(41)
+    pool = torch.from_numpy(W.serving_pool(nx_max=8192)).to(DEV)
+    reqs, outs, refs = _requests(zfpx_lib, pool, rng, 30)
+    sizes = []
+    for rq in reqs:
+        nb = -(-rq.nx // 4) * -(-rq.ny // 4) * -(-rq.nz // 4)
+        sizes.append(rq.nx * rq.ny * rq.nz * 4 + nb * 8 * rq.rate)
+    budget = 2 * max(sizes)
+    sv = zfpx_lib.Server(budget, max_slots=64)
+    for rq in reqs:
+        sv.submit(rq)
+    sv.drain(60.0)
+    st = sv.stats()
+    sv.close()
+    torch.cuda.synchronize()
+    assert st["max_inflight_bytes"] <= budget
+    _check(outs, refs)
+
+
+def test_server_rejects_bad_requests(zfpx_lib):
+    pool = torch.from_numpy(W.serving_pool(nx_max=1024)).to(DEV)
+    words = torch.zeros(1 << 16, dtype=torch.int64, device=DEV)
+    sv = zfpx_lib.Server(1 << 20, max_slots=4)
+    big = zfpx_lib.make_request(0, 8, pool, words)  # more bytes than the whole budget
+    with pytest.raises(zfpx_lib.ZfpxError) as e:
+        sv.submit(big)
+    assert e.value.status == zfpx_lib.EINVAL
+    bad = zfpx_lib.make_request(0, 0, pool[:, :4, :4], words)
+    with pytest.raises(zfpx_lib.ZfpxError):
+        sv.submit(bad)
+    sv.close()
+
+
+def test_replay_forms_agree(zfpx_lib):
+    rng = np.random.default_rng(42)
+    pool = torch.from_numpy(W.serving_pool(nx_max=4096)).to(DEV)
+    reqs, outs, refs = _requests(zfpx_lib, pool, rng, 40)
+    arrival = np.cumsum(rng.exponential(50e-6, len(reqs)))
+    arrival -= arrival[0]
+    sv = zfpx_lib.Server(64 << 30, max_slots=32)
+    lat = sv.replay(reqs, arrival, timeout_s=60.0)
+    sv.close()
+    torch.cuda.synchronize()
+    assert (lat > 0).all()
+    _check(outs, refs)
+    for o in outs:  # scribble, then the plain form must rebuild the same outputs
+        (o if isinstance(o, torch.Tensor) else o[0]).fill_(0)
+    lat2 = zfpx_lib.zfpx_plain_replay(reqs, arrival, timeout_s=60.0)
+    torch.cuda.synchronize()
+    assert (lat2 > 0).all()
+    _check(outs, refs)
