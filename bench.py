@@ -173,7 +173,10 @@ def main():
     serving = None
     if not args.no_serving:
         torch.cuda.empty_cache()
-        serving = serving_report(torch, zfpx, W, args.serving_requests)
+        try:
+            serving = serving_report(torch, zfpx, W, args.serving_requests)
+        except zfpx.ZfpxError as e:
+            serving = {"error": str(e)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -350,7 +353,7 @@ def serving_report(torch, zfpx, W, count):
     reqs, nbytes = build(base)
     zero = np.zeros(count)
     log(f"serving: saturated throughput ({count} requests at once, one launch each)")
-    lat = zfpx.zfpx_plain_replay(reqs, zero, timeout_s=300.0)
+    lat = zfpx.zfpx_plain_replay(reqs, zero, timeout_s=60.0)
     sat = nbytes.sum() / lat.max()
     mean_bytes = nbytes.mean()
     out = {"requests_per_point": count, "budget_bytes": 64 << 30,
@@ -364,9 +367,11 @@ def serving_report(torch, zfpx, W, count):
         reqs, nbytes = build(stream)
         log(f"serving: load {load:.2f}, mean gap {gap * 1e6:.1f} us")
         sv = zfpx.Server(64 << 30, max_slots=1024)
-        ls = sv.replay(reqs, arrival, timeout_s=300.0)
-        sv.close()
-        lp = zfpx.zfpx_plain_replay(reqs, arrival, timeout_s=300.0)
+        try:
+            ls = sv.replay(reqs, arrival, timeout_s=60.0)
+        finally:
+            sv.close()
+        lp = zfpx.zfpx_plain_replay(reqs, arrival, timeout_s=60.0)
         span_s = (arrival + ls).max()
         span_p = (arrival + lp).max()
         out["points"].append({

@@ -80,10 +80,17 @@ struct ServeCtl {        // host-coherent control block
   uint32_t pad;
 };
 
+struct ServeDevCtl {     // device-memory mirror written by the dispatcher
+  uint64_t published;    // requests copied into ring_dev
+  uint64_t stop;         // set once the host asked the loop to stop
+};
+
 struct ServeDev {        // arguments of the device loop
-  ServeCtl* ctl;         // device view of the control block
-  const ServeDesc* ring; // device view of the ring (cap entries)
+  ServeCtl* ctl;         // device view of the host control block
+  const ServeDesc* ring; // device view of the host ring (cap entries)
   uint64_t* done_flag;   // host-coherent, per slot: seq + 1 once complete
+  ServeDevCtl* dctl;     // device memory
+  ServeDesc* ring_dev;   // device memory copy of the ring
   uint64_t* claim;       // device memory, per slot: (seq << 32) | tiles claimed
   uint64_t* done;        // device memory, per slot: (seq << 32) | tiles done
   int32_t cap;

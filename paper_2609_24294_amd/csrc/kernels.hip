@@ -75,7 +75,16 @@ struct RegularGeo {
   }
 };
 
-template <bool VEC4>
+// COH: system-coherent element accesses that bypass the (per-XCD) L2, used by
+// the serving loop so that no cache write-back is needed between requests.
+__device__ __forceinline__ float coh_load(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void coh_store(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <bool VEC4, bool COH = false>
 __device__ __forceinline__ void gather(const float* __restrict__ src, const BlockView& v,
                                        float* val) {
 #pragma unroll
@@ -86,7 +95,7 @@ __device__ __forceinline__ void gather(const float* __restrict__ src, const Bloc
       int64_t base = v.rbase[dy] + zoff;
       int len = v.rlen[dy];
       float* o = val + 16 * dz + 4 * dy;
-      if (VEC4 && v.x0 + 3 < len) {
+      if (VEC4 && !COH && v.x0 + 3 < len) {
         f32x4 f = *reinterpret_cast<const f32x4*>(src + base + v.x0);
         o[0] = f.x;
         o[1] = f.y;
@@ -96,14 +105,14 @@ __device__ __forceinline__ void gather(const float* __restrict__ src, const Bloc
 #pragma unroll
         for (int dx = 0; dx < 4; dx++) {
           int x = v.x0 + dx < len ? v.x0 + dx : len - 1;
-          o[dx] = src[base + (int64_t)x * v.sx];
+          o[dx] = COH ? coh_load(src + base + (int64_t)x * v.sx) : src[base + (int64_t)x * v.sx];
         }
       }
     }
   }
 }
 
-template <bool VEC4>
+template <bool VEC4, bool COH = false>
 __device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView& v,
                                         const float* val) {
 #pragma unroll
@@ -116,13 +125,18 @@ __device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView
           int64_t base = v.rbase[dy] + zoff;
           int len = v.rlen[dy];
           const float* o = val + 16 * dz + 4 * dy;
-          if (VEC4 && v.x0 + 3 < len) {
+          if (VEC4 && !COH && v.x0 + 3 < len) {
             f32x4 f = {o[0], o[1], o[2], o[3]};
             *reinterpret_cast<f32x4*>(dst + base + v.x0) = f;
           } else {
 #pragma unroll
             for (int dx = 0; dx < 4; dx++)
-              if (v.x0 + dx < len) dst[base + (int64_t)(v.x0 + dx) * v.sx] = o[dx];
+              if (v.x0 + dx < len) {
+                if (COH)
+                  coh_store(dst + base + (int64_t)(v.x0 + dx) * v.sx, o[dx]);
+                else
+                  dst[base + (int64_t)(v.x0 + dx) * v.sx] = o[dx];
+              }
           }
         }
       }
@@ -134,7 +148,20 @@ __device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView
 // global memory (rate words per block, contiguous).  For rates dividing 64,
 // lane l always handles word l % rate of every (64/rate)-th block, so the
 // addresses are a per-lane base plus compile-time offsets.
-template <int RATE, bool TO_GLOBAL>
+template <bool COH>
+__device__ __forceinline__ void gstore64(uint64_t* p, uint64_t v) {
+  if (COH)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  else
+    *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ uint64_t gload64(const uint64_t* p) {
+  if (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  return *p;
+}
+
+template <int RATE, bool TO_GLOBAL, bool COH = false>
 __device__ __forceinline__ void copy_tile(uint64_t* __restrict__ g, uint64_t* lds, int lane,
                                           int nact, int rate_rt) {
   if constexpr (RATE > 0 && 64 % RATE == 0) {
@@ -146,9 +173,9 @@ __device__ __forceinline__ void copy_tile(uint64_t* __restrict__ g, uint64_t* ld
     for (int j = 0; j < RATE; j++) {
       if (b + j * step < nact) {
         if (TO_GLOBAL)
-          g[lane + 64 * j] = l[j * step * stride];
+          gstore64<COH>(g + lane + 64 * j, l[j * step * stride]);
         else
-          l[j * step * stride] = g[lane + 64 * j];
+          l[j * step * stride] = gload64<COH>(g + lane + 64 * j);
       }
     }
   } else {
@@ -159,9 +186,9 @@ __device__ __forceinline__ void copy_tile(uint64_t* __restrict__ g, uint64_t* ld
       int blk = w / rate;
       int idx = w - blk * rate;
       if (TO_GLOBAL)
-        g[w] = lds[blk * stride + idx];
+        gstore64<COH>(g + w, lds[blk * stride + idx]);
       else
-        lds[blk * stride + idx] = g[w];
+        lds[blk * stride + idx] = gload64<COH>(g + w);
     }
   }
 }
@@ -189,7 +216,7 @@ __device__ __forceinline__ int opaque(int x) {
 
 // One 64-block tile: gather + encode into the lane slices, then copy the
 // tile's words out (encode), or copy in + decode + scatter (decode).
-template <int RATE, bool VEC4, class Geo>
+template <int RATE, bool VEC4, bool COH = false, class Geo>
 __device__ __forceinline__ void encode_tile(const Geo& geo, const float* __restrict__ src,
                                             uint64_t* __restrict__ out, int rate, int lane,
                                             uint64_t* wlds, int32_t b0, int nact) {
@@ -200,28 +227,28 @@ __device__ __forceinline__ void encode_tile(const Geo& geo, const float* __restr
     BlockView v;
     geo.locate(b0 + lane, v);
     float val[64];
-    gather<VEC4>(src, v, val);
+    gather<VEC4, COH>(src, v, val);
     encode_block<RATE>(val, slice, rate);
   }
   wave_sync_lds();
-  copy_tile<RATE, true>(out + (int64_t)b0 * rate, wlds, opaque(lane), nact, rate);
+  copy_tile<RATE, true, COH>(out + (int64_t)b0 * rate, wlds, opaque(lane), nact, rate);
 }
 
-template <int RATE, bool VEC4, class Geo>
+template <int RATE, bool VEC4, bool COH = false, class Geo>
 __device__ __forceinline__ void decode_tile(const Geo& geo, const uint64_t* __restrict__ in,
                                             float* __restrict__ dst, int rate, int lane,
                                             uint64_t* wlds, int32_t b0, int nact) {
   const int stride = lds_stride(RATE > 0 ? RATE : rate);
   for (int i = (RATE > 0 ? RATE : rate); i < stride; i++) wlds[lane * stride + i] = 0;
-  copy_tile<RATE, false>(const_cast<uint64_t*>(in) + (int64_t)b0 * rate, wlds, lane, nact,
-                         rate);
+  copy_tile<RATE, false, COH>(const_cast<uint64_t*>(in) + (int64_t)b0 * rate, wlds, lane, nact,
+                              rate);
   wave_sync_lds();
   if (lane < nact) {
     float val[64];
     decode_block<RATE>(wlds + opaque(lane) * stride, val, rate);
     BlockView v;
     geo.locate(b0 + lane, v);
-    scatter<VEC4>(dst, v, val);
+    scatter<VEC4, COH>(dst, v, val);
   }
 }
 
@@ -279,31 +306,41 @@ __global__ __launch_bounds__(256) void k_decode(Geo geo, const uint64_t* __restr
 // ---------------------------------------------------------------------------
 // Serving loop
 // ---------------------------------------------------------------------------
-// Every wavefront is an independent worker.  It walks the request ring in
-// order (cursor = request number), claims 64-block tiles of the request at
-// its cursor with a compare-and-swap on a per-slot counter tagged with the
-// request number (so that a slot reused for a later request is never
-// confused with the earlier one), codes the tile, and counts it done; the
-// wavefront that completes a request's last tile raises the request's
-// completion flag in host memory.  Requests therefore overlap on the device
-// as soon as they are published.  Every wavefront leaves when the host sets
-// the stop flag, after `idle_ticks` without work, or after `max_ticks` in
-// total, so the grid always drains.
+// Wavefront 0 of workgroup 0 is the dispatcher: it alone polls the host's
+// control block (over PCIe, with a pause between polls) and copies newly
+// published descriptors into a ring in device memory, then publishes them to
+// the workers through a device-memory counter.  Every other wavefront is an
+// independent worker: it walks the device ring in order (cursor = request
+// number), claims 64-block tiles of the request at its cursor with a
+// compare-and-swap on a per-slot counter tagged with the request number (so a
+// slot reused for a later request is never confused with the earlier one),
+// codes the tile and counts it done; the wavefront that completes a request's
+// last tile raises the request's completion flag in host memory.  Requests
+// overlap on the device as soon as they are published.  Every wavefront
+// leaves when the host asks to stop, after `idle_ticks` without work, or after
+// `max_ticks` in total, so the grid always drains.
 
+// All control accesses of the loop are relaxed atomics: on this part an
+// acquire or release at agent or system scope means a whole-L2 invalidate or
+// write-back, far too costly per tile.  Ordering comes from the hardware
+// instead: coherent (cache-bypassing) atomic accesses, program order of
+// dependent loads, and explicit waits for outstanding memory operations
+// (s_waitcnt) before a store or atomic that publishes earlier writes.
 __device__ __forceinline__ uint64_t sys_load(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ uint32_t sys_load32(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-__device__ __forceinline__ uint64_t relaxed_sys_load(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
-__device__ __forceinline__ int64_t relaxed_sys_load_i(const int64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+__device__ __forceinline__ uint64_t dev_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ int32_t relaxed_sys_load_i32(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+__device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
+__device__ __forceinline__ int32_t dev_load32(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t dev_load64i(const int64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void serve_tile(const ServeDesc& q, int lane, uint64_t* wlds,
@@ -314,25 +351,66 @@ __device__ __forceinline__ void serve_tile(const ServeDesc& q, int lane, uint64_
   if (q.op == 0) {
     const float* src = reinterpret_cast<const float*>(q.in);
     uint64_t* out = reinterpret_cast<uint64_t*>(q.out);
-    if (q.vec4 && q.rate == 8)
-      encode_tile<8, true>(geo, src, out, 8, lane, wlds, b0, nact);
-    else if (q.vec4 && q.rate == 16)
-      encode_tile<16, true>(geo, src, out, 16, lane, wlds, b0, nact);
-    else if (q.vec4 && q.rate == 32)
-      encode_tile<32, true>(geo, src, out, 32, lane, wlds, b0, nact);
+    if (q.rate == 8)
+      encode_tile<8, false, true>(geo, src, out, 8, lane, wlds, b0, nact);
+    else if (q.rate == 16)
+      encode_tile<16, false, true>(geo, src, out, 16, lane, wlds, b0, nact);
+    else if (q.rate == 32)
+      encode_tile<32, false, true>(geo, src, out, 32, lane, wlds, b0, nact);
     else
-      encode_tile<0, false>(geo, src, out, q.rate, lane, wlds, b0, nact);
+      encode_tile<0, false, true>(geo, src, out, q.rate, lane, wlds, b0, nact);
   } else {
     const uint64_t* in = reinterpret_cast<const uint64_t*>(q.in);
     float* dst = reinterpret_cast<float*>(q.out);
-    if (q.vec4 && q.rate == 8)
-      decode_tile<8, true>(geo, in, dst, 8, lane, wlds, b0, nact);
-    else if (q.vec4 && q.rate == 16)
-      decode_tile<16, true>(geo, in, dst, 16, lane, wlds, b0, nact);
-    else if (q.vec4 && q.rate == 32)
-      decode_tile<32, true>(geo, in, dst, 32, lane, wlds, b0, nact);
+    if (q.rate == 8)
+      decode_tile<8, false, true>(geo, in, dst, 8, lane, wlds, b0, nact);
+    else if (q.rate == 16)
+      decode_tile<16, false, true>(geo, in, dst, 16, lane, wlds, b0, nact);
+    else if (q.rate == 32)
+      decode_tile<32, false, true>(geo, in, dst, 32, lane, wlds, b0, nact);
     else
-      decode_tile<0, false>(geo, in, dst, q.rate, lane, wlds, b0, nact);
+      decode_tile<0, false, true>(geo, in, dst, q.rate, lane, wlds, b0, nact);
+  }
+}
+
+constexpr int kDescWords = sizeof(ServeDesc) / sizeof(uint64_t);
+static_assert(sizeof(ServeDesc) % sizeof(uint64_t) == 0, "descriptor is whole words");
+static_assert(kDescWords <= 64, "one descriptor word per lane");
+
+// The dispatcher wavefront.
+__device__ __forceinline__ void serve_dispatch(const ServeDev d, int lane, uint64_t t_start) {
+  uint64_t seen = dev_load(&d.dctl->published);
+  uint64_t t_work = t_start;
+  for (;;) {
+    const uint64_t now = __builtin_amdgcn_s_memrealtime();
+    if (now - t_start > d.max_ticks) break;
+    if (sys_load32(&d.ctl->stop)) {
+      if (lane == 0)
+        __hip_atomic_store(&d.dctl->stop, uint64_t(1), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    const uint64_t hpub = sys_load(&d.ctl->published);
+    if (hpub > seen) {
+      for (uint64_t sq = seen; sq < hpub; sq++) {  // one descriptor word per lane
+        const int slot = (int)(sq % (uint64_t)d.cap);
+        const uint64_t* from = reinterpret_cast<const uint64_t*>(d.ring + slot);
+        uint64_t* to = reinterpret_cast<uint64_t*>(d.ring_dev + slot);
+        if (lane < kDescWords)
+          __hip_atomic_store(to + lane,
+                             __hip_atomic_load(from + lane, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_SYSTEM),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      wait_memory();  // the copies are in memory before they are published
+      if (lane == 0)
+        __hip_atomic_store(&d.dctl->published, hpub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      seen = hpub;
+      t_work = now;
+      continue;
+    }
+    if (now - t_work > d.idle_ticks) break;
+    __builtin_amdgcn_s_sleep(16);
   }
 }
 
@@ -340,50 +418,30 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
   extern __shared__ uint64_t lds[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(32);
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+  if (blockIdx.x == 0 && wave == 0) {
+    serve_dispatch(d, lane, t_start);
+    return;
+  }
+  uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(32);
   uint64_t t_work = t_start;
   uint64_t cursor = sys_load(&d.ctl->oldest);
-  uint64_t have = ~uint64_t(0);  // request whose descriptor is in q
-  ServeDesc q{};
   for (;;) {
     const uint64_t now = __builtin_amdgcn_s_memrealtime();
     if (now - t_start > d.max_ticks) break;
-    const uint64_t pub = sys_load(&d.ctl->published);
+    const uint64_t pub = dev_load(&d.dctl->published);
     if (cursor >= pub) {
-      if (sys_load32(&d.ctl->stop) || now - t_work > d.idle_ticks) break;
-      __builtin_amdgcn_s_sleep(4);
+      if (dev_load(&d.dctl->stop) || now - t_work > d.idle_ticks) break;
+      __builtin_amdgcn_s_sleep(32);
       continue;
     }
     const int slot = (int)(cursor % (uint64_t)d.cap);
-    if (have != cursor) {
-      const ServeDesc* r = d.ring + slot;
-      q.seq = relaxed_sys_load(&r->seq);
-      if (q.seq != cursor) {  // the slot already holds a later request
-        cursor++;
-        continue;
-      }
-      q.op = relaxed_sys_load_i32(&r->op);
-      q.rate = relaxed_sys_load_i32(&r->rate);
-      q.nblocks = relaxed_sys_load_i32(&r->nblocks);
-      q.ntiles = relaxed_sys_load_i32(&r->ntiles);
-      q.vec4 = relaxed_sys_load_i32(&r->vec4);
-      q.geo.nx = relaxed_sys_load_i(&r->geo.nx);
-      q.geo.ny = relaxed_sys_load_i(&r->geo.ny);
-      q.geo.nz = relaxed_sys_load_i(&r->geo.nz);
-      q.geo.sx = relaxed_sys_load_i(&r->geo.sx);
-      q.geo.sy = relaxed_sys_load_i(&r->geo.sy);
-      q.geo.sz = relaxed_sys_load_i(&r->geo.sz);
-      q.geo.nbx = relaxed_sys_load_i32(&r->geo.nbx);
-      q.geo.nby = relaxed_sys_load_i32(&r->geo.nby);
-      q.in = relaxed_sys_load(&r->in);
-      q.out = relaxed_sys_load(&r->out);
-      have = cursor;
-    }
-    // claim a tile (lane 0), then share the result with the wavefront
-    int32_t tile = -1;
+    // claim a tile (lane 0) with a fetch-add on the slot's counter, whose
+    // high half names the request it counts for; share the result
+    uint64_t got = ~uint64_t(0);  // (request tag << 32) | tile, or ~0 = none
     if (lane == 0) {
       const uint32_t want = (uint32_t)cursor;
+      const int32_t ntiles = dev_load32(&d.ring_dev[slot].ntiles);
       for (;;) {
         uint64_t c = __hip_atomic_load(d.claim + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t cseq = (uint32_t)(c >> 32), cnt = (uint32_t)c;
@@ -395,33 +453,63 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
             __hip_atomic_compare_exchange_strong(d.done + slot, &dv, (uint64_t)want << 32,
                                                  __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
+          wait_memory();  // the done counter is reset before tiles can be claimed
           __hip_atomic_compare_exchange_strong(d.claim + slot, &c, (uint64_t)want << 32,
-                                               __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
           continue;
         }
-        if ((int32_t)cnt >= q.ntiles) break;  // every tile already claimed
-        if (__hip_atomic_compare_exchange_strong(d.claim + slot, &c, c + 1, __ATOMIC_ACQ_REL,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          tile = (int32_t)cnt;
-          break;
-        }
+        if ((int32_t)cnt >= ntiles) break;  // every tile already claimed
+        // the counter may have moved on to a later request since the load: the
+        // tile returned then belongs to that request and is processed for it
+        got = __hip_atomic_fetch_add(d.claim + slot, uint64_t(1), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
     }
-    tile = __shfl(tile, 0, 64);
-    if (tile < 0) {
+    got = __shfl(got, 0, 64);
+    if (got == ~uint64_t(0)) {
       cursor++;
       continue;
     }
+    const uint32_t gseq = (uint32_t)(got >> 32);
+    const int32_t tile = (int32_t)(uint32_t)got;
+    const ServeDesc* r = d.ring_dev + slot;
+    ServeDesc q;
+    q.seq = dev_load(&r->seq);
+    q.ntiles = dev_load32(&r->ntiles);
+    if ((uint32_t)q.seq != gseq || tile >= q.ntiles) {
+      // overshoot past the last tile (or a slot reused twice meanwhile): nothing to do
+      if ((uint32_t)q.seq == (uint32_t)cursor) continue;
+      cursor++;
+      continue;
+    }
+    q.op = dev_load32(&r->op);
+    q.rate = dev_load32(&r->rate);
+    q.nblocks = dev_load32(&r->nblocks);
+    q.vec4 = dev_load32(&r->vec4);
+    q.pad = 0;
+    q.geo.nx = dev_load64i(&r->geo.nx);
+    q.geo.ny = dev_load64i(&r->geo.ny);
+    q.geo.nz = dev_load64i(&r->geo.nz);
+    q.geo.sx = dev_load64i(&r->geo.sx);
+    q.geo.sy = dev_load64i(&r->geo.sy);
+    q.geo.sz = dev_load64i(&r->geo.sz);
+    q.geo.nbx = dev_load32(&r->geo.nbx);
+    q.geo.nby = dev_load32(&r->geo.nby);
+    q.in = dev_load(&r->in);
+    q.out = dev_load(&r->out);
     serve_tile(q, opaque(lane), wlds, tile);
     wave_sync_lds();
-    // make the tile's output visible before counting it done
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    // the tile's output was written through to memory (system-coherent
+    // stores); wait until every store of the wavefront has completed before
+    // counting the tile done, so no cache write-back is needed
+    wait_memory();
     if (lane == 0) {
-      uint64_t prev = __hip_atomic_fetch_add(d.done + slot, 1, __ATOMIC_ACQ_REL,
-                                             __HIP_MEMORY_SCOPE_SYSTEM);
+      uint64_t prev = __hip_atomic_fetch_add(d.done + slot, 1, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
       if ((int32_t)(uint32_t)prev + 1 == q.ntiles)
-        __hip_atomic_store(d.done_flag + slot, cursor + 1, __ATOMIC_RELEASE,
+        __hip_atomic_store(d.done_flag + slot, q.seq + 1, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_SYSTEM);
     }
     t_work = __builtin_amdgcn_s_memrealtime();

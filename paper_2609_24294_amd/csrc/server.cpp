@@ -90,6 +90,8 @@ struct zfpx_server {
   uint64_t* flags_d = nullptr;
   uint64_t* claim = nullptr;  // device memory
   uint64_t* done = nullptr;
+  ServeDevCtl* dctl = nullptr;
+  ServeDesc* ring_dev = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t loop_done = nullptr;
   bool loop_running = false;
@@ -111,6 +113,8 @@ static void server_free(zfpx_server* sv) {
   if (sv->stream) (void)hipStreamDestroy(sv->stream);
   if (sv->claim) (void)hipFree(sv->claim);
   if (sv->done) (void)hipFree(sv->done);
+  if (sv->dctl) (void)hipFree(sv->dctl);
+  if (sv->ring_dev) (void)hipFree(sv->ring_dev);
   if (sv->ctl) (void)hipHostFree(sv->ctl);
   if (sv->ring) (void)hipHostFree(sv->ring);
   if (sv->flags) (void)hipHostFree(sv->flags);
@@ -132,6 +136,8 @@ static int ensure_loop(zfpx_server* sv) {
   d.ctl = sv->ctl_d;
   d.ring = sv->ring_d;
   d.done_flag = sv->flags_d;
+  d.dctl = sv->dctl;
+  d.ring_dev = sv->ring_dev;
   d.claim = sv->claim;
   d.done = sv->done;
   d.cap = sv->cap;
@@ -238,9 +244,22 @@ int zfpx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t workg
     return ZFPX_EHIP;
   }
   if (hipMalloc((void**)&sv->claim, sizeof(uint64_t) * max_slots) != hipSuccess ||
-      hipMalloc((void**)&sv->done, sizeof(uint64_t) * max_slots) != hipSuccess) {
+      hipMalloc((void**)&sv->done, sizeof(uint64_t) * max_slots) != hipSuccess ||
+      hipMalloc((void**)&sv->dctl, sizeof(ServeDevCtl)) != hipSuccess ||
+      hipMalloc((void**)&sv->ring_dev, sizeof(ServeDesc) * max_slots) != hipSuccess) {
     server_free(sv);
     return ZFPX_ENOMEM;
+  }
+  {
+    ServeDevCtl z{0, 0};
+    std::vector<ServeDesc> blank(max_slots);
+    memset(blank.data(), 0xff, sizeof(ServeDesc) * max_slots);
+    if (hipMemcpy(sv->dctl, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(sv->ring_dev, blank.data(), sizeof(ServeDesc) * max_slots,
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      server_free(sv);
+      return ZFPX_EHIP;
+    }
   }
   // tag every slot with a request number that precedes any real one
   std::vector<uint64_t> init(max_slots, (uint64_t)0xffffffffu << 32);
