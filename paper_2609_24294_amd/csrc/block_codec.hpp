@@ -162,27 +162,78 @@ ZFPX_HD void transpose32(uint32_t* a) {
 }
 
 // Two independent 32x32 transposes at once on 64-bit words: a[r] holds row r
-// of the first matrix in its low half and of the second in its high half.
-// The stage masks never let a bit cross the 32-bit boundary, so afterwards
-// a[r] low/high bit c = old a[c] low/high bit r.
-template <int J, uint64_t MASK>
-ZFPX_HD void transpose_stage64(uint64_t* a) {
+// of the first matrix in its low half and of the second in its high half;
+// afterwards a[r] low/high bit c = old a[c] low/high bit r.  The classic
+// five-stage block-swap transpose: stage J swaps, between rows r and r+J
+// (r & J == 0), the bits whose column has bit J set in row r with the bits
+// whose column has it clear in row r+J.  Stages 16 and 8 move whole bytes
+// (one byte permute per output half); stages 4, 2, 1 are a shift and a
+// bit-field select per output half (the masks keep bits from crossing the
+// 32-bit boundary, so the shifts can act on the 64-bit word).
+
+// Byte permute: result byte i = byte sel_i of (hi:lo), bytes 0-3 from lo.
+ZFPX_HD uint32_t byte_perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_perm(hi, lo, sel);
+#else
+  uint64_t x = ((uint64_t)hi << 32) | lo;
+  uint32_t r = 0;
+  for (int i = 0; i < 4; i++) r |= (uint32_t)((x >> (8 * ((sel >> (8 * i)) & 7))) & 0xff) << (8 * i);
+  return r;
+#endif
+}
+
+template <int J>
+ZFPX_HD void transpose_bytes64(uint64_t* a) {
+  // J = 16: new a = [a.b0 a.b1 b.b0 b.b1], new b = [a.b2 a.b3 b.b2 b.b3]
+  // J = 8 : new a = [a.b0 b.b0 a.b2 b.b2], new b = [a.b1 b.b1 a.b3 b.b3]
+  constexpr uint32_t sa = J == 16 ? 0x05040100u : 0x06020400u;
+  constexpr uint32_t sb = J == 16 ? 0x07060302u : 0x07030501u;
 #pragma unroll
   for (int r = 0; r < 32; r++) {
     if ((r & J) == 0) {
-      uint64_t t = ((a[r] >> J) ^ a[r + J]) & MASK;
-      a[r + J] ^= t;
-      a[r] ^= t << J;
+      uint32_t alo = (uint32_t)a[r], ahi = (uint32_t)(a[r] >> 32);
+      uint32_t blo = (uint32_t)a[r + J], bhi = (uint32_t)(a[r + J] >> 32);
+      a[r] = byte_perm(blo, alo, sa) | ((uint64_t)byte_perm(bhi, ahi, sa) << 32);
+      a[r + J] = byte_perm(blo, alo, sb) | ((uint64_t)byte_perm(bhi, ahi, sb) << 32);
+    }
+  }
+}
+
+// Bit select: (a & m) | (b & ~m), one three-input logic instruction.
+ZFPX_HD uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA);
+#else
+  return (a & m) | (b & ~m);
+#endif
+}
+
+ZFPX_HD uint64_t bit_select64(uint64_t m, uint64_t a, uint64_t b) {
+  return (uint64_t)bit_select((uint32_t)m, (uint32_t)a, (uint32_t)b) |
+         ((uint64_t)bit_select((uint32_t)(m >> 32), (uint32_t)(a >> 32), (uint32_t)(b >> 32))
+          << 32);
+}
+
+template <int J, uint64_t MASK>
+ZFPX_HD void transpose_bits64(uint64_t* a) {
+  constexpr uint64_t HM = MASK << J;
+#pragma unroll
+  for (int r = 0; r < 32; r++) {
+    if ((r & J) == 0) {
+      uint64_t x = a[r], y = a[r + J];
+      a[r + J] = bit_select64(MASK, x >> J, y);
+      a[r] = bit_select64(HM, y << J, x);
     }
   }
 }
 
 ZFPX_HD void transpose32x2(uint64_t* a) {
-  transpose_stage64<16, 0x0000ffff0000ffffull>(a);
-  transpose_stage64<8, 0x00ff00ff00ff00ffull>(a);
-  transpose_stage64<4, 0x0f0f0f0f0f0f0f0full>(a);
-  transpose_stage64<2, 0x3333333333333333ull>(a);
-  transpose_stage64<1, 0x5555555555555555ull>(a);
+  transpose_bytes64<16>(a);
+  transpose_bytes64<8>(a);
+  transpose_bits64<4, 0x0f0f0f0f0f0f0f0full>(a);
+  transpose_bits64<2, 0x3333333333333333ull>(a);
+  transpose_bits64<1, 0x5555555555555555ull>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -299,6 +350,7 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt) {
   for (int k = 31; k >= 0; k--) {
     uint64_t x = 0;
     if (pos < maxbits) {
+      // w holds the stream bits from `pos` on; `avail` of them are valid
       uint64_t w = window64(in, pos);
       int m = (int)(maxbits - pos) < n ? (int)(maxbits - pos) : n;
       x = w & low_mask(m);
@@ -306,18 +358,28 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt) {
       if (n < 64 && pos < maxbits) {
         int g = (int)((w >> m) & 1);  // first group test (m < 64 here)
         pos += 1;
+        w = (w >> m) >> 1;
+        int avail = 63 - m;
         while (g) {
-          uint64_t s = window64(in, pos);  // the scan
+          // scan: zeros up to the next one, at most lim positions
           int lim = 63 - n;
           if ((int)(maxbits - pos) < lim) lim = (int)(maxbits - pos);
-          int z = s ? ctz64(s) : 64;
+          // the scan and the next group test need up to lim + 2 bits
+          if (avail < lim + 2 && (w == 0 || ctz64(w) + 2 > avail)) {
+            w = window64(in, pos);
+            avail = 64;
+          }
+          int z = w ? ctz64(w) : 64;
           int t = z < lim ? z : lim;
           int found = z < lim;
           x |= uint64_t(1) << (n + t);
           n += t + 1;
           pos += t + found;
-          g = (n < 64 && pos < maxbits) ? (int)((s >> (t + found)) & 1) : 0;
+          int used = t + found;  // <= 63
+          g = (n < 64 && pos < maxbits) ? (int)((w >> used) & 1) : 0;
           pos += n < 64 ? 1 : 0;
+          w = (w >> used) >> 1;
+          avail -= used + 1;
         }
       }
     }
