@@ -209,21 +209,19 @@ ZFPX_HD uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
 #endif
 }
 
-ZFPX_HD uint64_t bit_select64(uint64_t m, uint64_t a, uint64_t b) {
-  return (uint64_t)bit_select((uint32_t)m, (uint32_t)a, (uint32_t)b) |
-         ((uint64_t)bit_select((uint32_t)(m >> 32), (uint32_t)(a >> 32), (uint32_t)(b >> 32))
-          << 32);
-}
-
-template <int J, uint64_t MASK>
+template <int J, uint32_t MASK>
 ZFPX_HD void transpose_bits64(uint64_t* a) {
-  constexpr uint64_t HM = MASK << J;
+  // Each half is shifted on its own: the bits a 64-bit shift would carry
+  // across the halves land where the select mask discards them.
+  constexpr uint32_t HM = MASK << J;
 #pragma unroll
   for (int r = 0; r < 32; r++) {
     if ((r & J) == 0) {
-      uint64_t x = a[r], y = a[r + J];
-      a[r + J] = bit_select64(MASK, x >> J, y);
-      a[r] = bit_select64(HM, y << J, x);
+      uint32_t xl = (uint32_t)a[r], xh = (uint32_t)(a[r] >> 32);
+      uint32_t yl = (uint32_t)a[r + J], yh = (uint32_t)(a[r + J] >> 32);
+      a[r + J] = (uint64_t)bit_select(MASK, xl >> J, yl) |
+                 ((uint64_t)bit_select(MASK, xh >> J, yh) << 32);
+      a[r] = (uint64_t)bit_select(HM, yl << J, xl) | ((uint64_t)bit_select(HM, yh << J, xh) << 32);
     }
   }
 }
@@ -231,9 +229,9 @@ ZFPX_HD void transpose_bits64(uint64_t* a) {
 ZFPX_HD void transpose32x2(uint64_t* a) {
   transpose_bytes64<16>(a);
   transpose_bytes64<8>(a);
-  transpose_bits64<4, 0x0f0f0f0f0f0f0f0full>(a);
-  transpose_bits64<2, 0x3333333333333333ull>(a);
-  transpose_bits64<1, 0x5555555555555555ull>(a);
+  transpose_bits64<4, 0x0f0f0f0fu>(a);
+  transpose_bits64<2, 0x33333333u>(a);
+  transpose_bits64<1, 0x55555555u>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,18 +307,41 @@ ZFPX_HD void encode_block(float* v, uint64_t* out, int rate_rt) {
     if (pos < maxbits) {
       uint64_t x = X[k];
       uint64_t y = n < 64 ? (x >> n) : 0;  // bits not yet significant
-      or_bits(out, pos, x ^ (y << n));     // the first n bits verbatim
+      or_bits(out, pos, x & low_mask(n));  // the first n bits verbatim
       pos += n;
-      while (y != 0 && pos < maxbits) {
-        // group test 1, zeros up to the next set bit, then that bit (the
-        // bit at position 63 is implied and not written)
-        int p = ctz64(y);
-        int last = (n + p == 63);
-        uint64_t code = last ? uint64_t(1) : (uint64_t(1) | (uint64_t(2) << p));
-        or_bits(out, pos, code);
-        pos += p + 2 - last;
-        n += p + 1;
-        y = (y >> p) >> 1;
+      if (y != 0 && pos < maxbits) {
+        // Each newly significant coefficient costs a group test 1, the zeros
+        // up to it and its own 1 (that one is implied, and not written, for
+        // coefficient 63).  Common case: all of the plane's groups fit one
+        // 64-bit code word and none reaches coefficient 63; the word is then
+        // written at once.  Groups that start past the budget only land in
+        // the slack words, and the budget is spent either way, so the coded
+        // bits are those of the group-by-group loop below.
+        bool done = false;
+        uint64_t code = 0, r = y;
+        int len = 0, c = 0;
+        while (r != 0) {
+          int p = ctz64(r);
+          code |= (uint64_t(1) | (uint64_t(2) << p)) << (len & 63);
+          len += p + 2;
+          c += p + 1;
+          r = (r >> p) >> 1;
+        }
+        if (len <= 64 && n + c <= 63) {
+          or_bits(out, pos, code);
+          pos += len;
+          n += c;
+          done = true;
+        }
+        while (!done && y != 0 && pos < maxbits) {
+          int p = ctz64(y);
+          int last = (n + p == 63);
+          uint64_t g = last ? uint64_t(1) : (uint64_t(1) | (uint64_t(2) << p));
+          or_bits(out, pos, g);
+          pos += p + 2 - last;
+          n += p + 1;
+          y = (y >> p) >> 1;
+        }
       }
       pos += n < 64 ? 1 : 0;  // group test 0 (a zero bit)
     }
@@ -350,36 +371,62 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt) {
   for (int k = 31; k >= 0; k--) {
     uint64_t x = 0;
     if (pos < maxbits) {
-      // w holds the stream bits from `pos` on; `avail` of them are valid
-      uint64_t w = window64(in, pos);
       int m = (int)(maxbits - pos) < n ? (int)(maxbits - pos) : n;
-      x = w & low_mask(m);
+      x = window64(in, pos) & low_mask(m);  // the first n bits verbatim
       pos += m;
       if (n < 64 && pos < maxbits) {
-        int g = (int)((w >> m) & 1);  // first group test (m < 64 here)
-        pos += 1;
-        w = (w >> m) >> 1;
-        int avail = 63 - m;
-        while (g) {
-          // scan: zeros up to the next one, at most lim positions
-          int lim = 63 - n;
-          if ((int)(maxbits - pos) < lim) lim = (int)(maxbits - pos);
-          // the scan and the next group test need up to lim + 2 bits
-          if (avail < lim + 2 && (w == 0 || ctz64(w) + 2 > avail)) {
-            w = window64(in, pos);
-            avail = 64;
+        // Common case first: every group test and scan of the plane lies in
+        // one 64-bit window, inside the budget, and no scan reaches
+        // coefficient 63 (whose one would be implied).  Otherwise the plane
+        // is decoded group by group from the same state.
+        bool done = false;
+        uint64_t s = window64(in, pos);
+        uint64_t y = 0;
+        int c = 0, used = 1;  // coefficients and bits taken; the closing zero
+        while (s & 1) {
+          uint64_t r = s >> 1;
+          // no one left in the window: t = 64 ends the loop and fails the
+          // window test below
+          int t = r != 0 ? ctz64(r) : 64;
+          y |= uint64_t(1) << ((c + t) & 63);
+          c += t + 1;
+          used += t + 2;
+          s = (r >> (t & 63)) >> 1;
+          if (t == 64) s = 0;
+        }
+        if (used <= 64 && pos + used <= maxbits && n + c <= 63) {
+          x |= y << n;
+          n += c;
+          pos += used;
+          done = true;
+        }
+        if (!done) {
+          uint64_t w = window64(in, pos);
+          int g = (int)(w & 1);  // first group test
+          pos += 1;
+          w >>= 1;
+          int avail = 63;
+          while (g) {
+            // scan: zeros up to the next one, at most lim positions
+            int lim = 63 - n;
+            if ((int)(maxbits - pos) < lim) lim = (int)(maxbits - pos);
+            // the scan and the next group test need up to lim + 2 bits
+            if (avail < lim + 2 && (w == 0 || ctz64(w) + 2 > avail)) {
+              w = window64(in, pos);
+              avail = 64;
+            }
+            int z = w ? ctz64(w) : 64;
+            int t = z < lim ? z : lim;
+            int found = z < lim;
+            x |= uint64_t(1) << (n + t);
+            n += t + 1;
+            pos += t + found;
+            int u = t + found;  // <= 63
+            g = (n < 64 && pos < maxbits) ? (int)((w >> u) & 1) : 0;
+            pos += n < 64 ? 1 : 0;
+            w = (w >> u) >> 1;
+            avail -= u + 1;
           }
-          int z = w ? ctz64(w) : 64;
-          int t = z < lim ? z : lim;
-          int found = z < lim;
-          x |= uint64_t(1) << (n + t);
-          n += t + 1;
-          pos += t + found;
-          int used = t + found;  // <= 63
-          g = (n < 64 && pos < maxbits) ? (int)((w >> used) & 1) : 0;
-          pos += n < 64 ? 1 : 0;
-          w = (w >> used) >> 1;
-          avail -= used + 1;
         }
       }
     }

@@ -84,9 +84,35 @@ __device__ __forceinline__ void coh_store(float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// A whole block: 4 levels and 4 rows present, its 4 points inside every row,
+// unit x stride.
+__device__ __forceinline__ bool whole_block(const BlockView& v) {
+  int len = min(min(v.rlen[0], v.rlen[1]), min(v.rlen[2], v.rlen[3]));
+  return v.nlev == 4 && v.nrow == 4 && v.sx == 1 && v.x0 + 3 < len;
+}
+
+// Gather the 64 values of a block.  A whole block takes sixteen 16-byte
+// loads with no branch between them, so that all of them are in flight at
+// once; any other block loads every element from its clamped position
+// (repeating the last level, row or point), also without branches.
 template <bool VEC4, bool COH = false>
 __device__ __forceinline__ void gather(const float* __restrict__ src, const BlockView& v,
                                        float* val) {
+  if (VEC4 && !COH && whole_block(v)) {
+#pragma unroll
+    for (int dz = 0; dz < 4; dz++) {
+#pragma unroll
+      for (int dy = 0; dy < 4; dy++) {
+        f32x4 f = *reinterpret_cast<const f32x4*>(src + v.rbase[dy] + dz * v.lstride + v.x0);
+        float* o = val + 16 * dz + 4 * dy;
+        o[0] = f.x;
+        o[1] = f.y;
+        o[2] = f.z;
+        o[3] = f.w;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int dz = 0; dz < 4; dz++) {
     int64_t zoff = (int64_t)(dz < v.nlev ? dz : v.nlev - 1) * v.lstride;
@@ -95,18 +121,10 @@ __device__ __forceinline__ void gather(const float* __restrict__ src, const Bloc
       int64_t base = v.rbase[dy] + zoff;
       int len = v.rlen[dy];
       float* o = val + 16 * dz + 4 * dy;
-      if (VEC4 && !COH && v.x0 + 3 < len) {
-        f32x4 f = *reinterpret_cast<const f32x4*>(src + base + v.x0);
-        o[0] = f.x;
-        o[1] = f.y;
-        o[2] = f.z;
-        o[3] = f.w;
-      } else {
 #pragma unroll
-        for (int dx = 0; dx < 4; dx++) {
-          int x = v.x0 + dx < len ? v.x0 + dx : len - 1;
-          o[dx] = COH ? coh_load(src + base + (int64_t)x * v.sx) : src[base + (int64_t)x * v.sx];
-        }
+      for (int dx = 0; dx < 4; dx++) {
+        int x = v.x0 + dx < len ? v.x0 + dx : len - 1;
+        o[dx] = COH ? coh_load(src + base + (int64_t)x * v.sx) : src[base + (int64_t)x * v.sx];
       }
     }
   }
@@ -115,6 +133,18 @@ __device__ __forceinline__ void gather(const float* __restrict__ src, const Bloc
 template <bool VEC4, bool COH = false>
 __device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView& v,
                                         const float* val) {
+  if (VEC4 && !COH && whole_block(v)) {
+#pragma unroll
+    for (int dz = 0; dz < 4; dz++) {
+#pragma unroll
+      for (int dy = 0; dy < 4; dy++) {
+        const float* o = val + 16 * dz + 4 * dy;
+        f32x4 f = {o[0], o[1], o[2], o[3]};
+        *reinterpret_cast<f32x4*>(dst + v.rbase[dy] + dz * v.lstride + v.x0) = f;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int dz = 0; dz < 4; dz++) {
     if (dz < v.nlev) {
