@@ -25,11 +25,13 @@ bool rate_ok(int rate) { return rate >= 1 && rate <= 32; }
 int64_t ceil4(int64_t n) { return (n + 3) / 4; }
 bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 
-LaunchCfg default_cfg(int rate) {
+// One wavefront per workgroup: a finished wavefront frees its slot at once
+// instead of waiting for the slowest wavefront of its workgroup (coding time
+// varies from tile to tile).
+LaunchCfg default_cfg(int) {
   LaunchCfg c;
-  c.wg = 256;
+  c.wg = 64;
   c.grid = 0;
-  while (c.wg > 64 && lds_bytes(c.wg, rate) > device_max_lds()) c.wg /= 2;
   return c;
 }
 

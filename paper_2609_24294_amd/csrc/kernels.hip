@@ -32,8 +32,16 @@ struct BlockView {
   int32_t x0;  // first x of the block
 };
 
+// Loads through the constant address space: with a wave-uniform address they
+// become scalar loads (no per-lane round trip).
+template <class T>
+__device__ __forceinline__ T uniform_load(const T* p, int64_t i) {
+  return ((const __attribute__((address_space(4))) T*)p)[i];
+}
+
 struct PlanGeo {
   PlanDev p;
+  // Any block: find its run from the run table.
   __device__ __forceinline__ void locate(int32_t b, BlockView& v) const {
     int32_t s = p.tile_seg[b >> 6];
     while (p.seg_block0[s + 1] <= b) s++;
@@ -48,6 +56,43 @@ struct PlanGeo {
     v.nlev = d.nlev;
     v.nrow = d.nrow;
     v.x0 = 4 * (b - d.block0);
+  }
+  // Block b0 + lane of a tile whose first block b0 is the same on every lane
+  // and whose last active block is b0 + nact - 1.  A tile that meets at most
+  // two runs reads both descriptors with scalar loads and each lane picks
+  // its own; other tiles look every block up.
+  __device__ __forceinline__ void locate_tile(int32_t b0, int lane, int nact,
+                                              BlockView& v) const {
+    int32_t s = uniform_load(p.tile_seg, b0 >> 6);
+    while (uniform_load(p.seg_block0, s + 1) <= b0) s++;
+    const int32_t last = b0 + nact - 1;
+    const int32_t e1 = uniform_load(p.seg_block0, s + 1);
+    // e1 <= last < total blocks, so run s + 1 exists and so does entry s + 2
+    if (e1 <= last && uniform_load(p.seg_block0, s + 2) <= last) {
+      locate(b0 + lane, v);
+      return;
+    }
+    const int32_t b = b0 + lane;
+    const int32_t s1 = e1 <= last ? s + 1 : s;
+    const bool second = b >= e1;
+    const SegDesc* d0 = p.segs + s;
+    const SegDesc* d1 = p.segs + s1;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int64_t r0 = uniform_load(&d0->rbase[i], 0), r1 = uniform_load(&d1->rbase[i], 0);
+      const int32_t l0 = uniform_load(&d0->rlen[i], 0), l1 = uniform_load(&d1->rlen[i], 0);
+      v.rbase[i] = second ? r1 : r0;
+      v.rlen[i] = second ? l1 : l0;
+    }
+    const int64_t ls0 = uniform_load(&d0->lstride, 0), ls1 = uniform_load(&d1->lstride, 0);
+    const int32_t nl0 = uniform_load(&d0->nlev, 0), nl1 = uniform_load(&d1->nlev, 0);
+    const int32_t nr0 = uniform_load(&d0->nrow, 0), nr1 = uniform_load(&d1->nrow, 0);
+    const int32_t bb0 = uniform_load(&d0->block0, 0), bb1 = uniform_load(&d1->block0, 0);
+    v.lstride = second ? ls1 : ls0;
+    v.sx = 1;
+    v.nlev = second ? nl1 : nl0;
+    v.nrow = second ? nr1 : nr0;
+    v.x0 = 4 * (b - (second ? bb1 : bb0));
   }
 };
 
@@ -72,6 +117,9 @@ struct RegularGeo {
     v.nlev = (int32_t)(g.nz - z0 < 4 ? g.nz - z0 : 4);
     v.nrow = (int32_t)(g.ny - y0 < 4 ? g.ny - y0 : 4);
     v.x0 = (int32_t)(4 * bx);
+  }
+  __device__ __forceinline__ void locate_tile(int32_t b0, int lane, int, BlockView& v) const {
+    locate(b0 + lane, v);
   }
 };
 
@@ -255,7 +303,7 @@ __device__ __forceinline__ void encode_tile(const Geo& geo, const float* __restr
   for (int i = 0; i < stride; i++) slice[i] = 0;
   if (lane < nact) {
     BlockView v;
-    geo.locate(b0 + lane, v);
+    geo.locate_tile(b0, lane, nact, v);
     float val[64];
     gather<VEC4, COH>(src, v, val);
     encode_block<RATE>(val, slice, rate);
@@ -277,7 +325,7 @@ __device__ __forceinline__ void decode_tile(const Geo& geo, const uint64_t* __re
     float val[64];
     decode_block<RATE>(wlds + opaque(lane) * stride, val, rate);
     BlockView v;
-    geo.locate(b0 + lane, v);
+    geo.locate_tile(b0, lane, nact, v);
     scatter<VEC4, COH>(dst, v, val);
   }
 }
@@ -291,7 +339,7 @@ __global__ __launch_bounds__(256) void k_encode(Geo geo, const float* __restrict
   extern __shared__ uint64_t lds[];
   const int rate = RATE > 0 ? RATE : rate_rt;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int waves = blockDim.x >> 6;
   uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(rate);
   const int32_t ntiles = (b_end - b_begin + 63) >> 6;
@@ -308,14 +356,17 @@ __global__ __launch_bounds__(256) void k_encode(Geo geo, const float* __restrict
   }
 }
 
+// The decoder is latency bound (a serial chain of LDS reads through each
+// block's planes): a fourth wavefront per SIMD pays for the few registers
+// this spills.
 template <int RATE, bool VEC4, bool PERSIST, class Geo>
-__global__ __launch_bounds__(256) void k_decode(Geo geo, const uint64_t* __restrict__ in,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_decode(Geo geo, const uint64_t* __restrict__ in,
                                                 float* __restrict__ dst, int rate_rt,
                                                 int32_t b_begin, int32_t b_end) {
   extern __shared__ uint64_t lds[];
   const int rate = RATE > 0 ? RATE : rate_rt;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int waves = blockDim.x >> 6;
   uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(rate);
   const int32_t ntiles = (b_end - b_begin + 63) >> 6;
