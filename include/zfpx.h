@@ -249,10 +249,11 @@ int zfpx_graph_destroy(zfpx_graph* graph);
  * flight.  Results are bit-identical to the one-request launch form.
  *
  *   zfpx_server_create : max_slots ring entries (1..65536); workgroups of the
- *                        device loop (0 = 4 per compute unit).  Allocates
+ *                        device loop (0 = 2 per compute unit).  Allocates
  *                        pinned host memory and device memory.
  *   zfpx_server_submit : queue a request; EINVAL if malformed or larger than
- *                        the whole budget, EAGAIN if the queue is full.
+ *                        the whole budget, EAGAIN if the queue is full,
+ *                        ESTATE once a server has taken 2^32 - 1 requests.
  *                        Thread-safe.  Returns a ticket.
  *   zfpx_server_progress / _poll : collect completions and admit more;
  *                        poll reports done and the latency (seconds from

@@ -68,7 +68,9 @@ struct ServeDesc {   // one admitted request; host-coherent memory, slot = seq %
   int32_t op;        // 0 = encode (float32 -> words), 1 = decode
   int32_t rate;
   int32_t nblocks, ntiles;
-  int32_t vec4, pad;
+  uint32_t vspan;     // float32 array span in bytes when it is 16-byte accessible
+                      // within 4 GiB (unit x stride, aligned rows), else 0
+  int32_t per_claim;  // tiles a wavefront takes with one claim (1..8)
   RegularDev geo;
   uint64_t in, out;  // device addresses
 };

@@ -132,6 +132,18 @@ __device__ __forceinline__ void coh_store(float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// System-coherent 16-byte accesses for the serving loop, through a buffer
+// resource over the request's array (base and size wave-uniform): loads miss
+// the per-XCD L2 and stores write through to memory (scope bits sc0 sc1), so
+// no cache invalidation or write-back is needed between requests.  Offsets
+// past the resource read zero and drop stores.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kSystemScope = 1 | 16;  // sc0 | sc1
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t coh_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
 // A whole block: 4 levels and 4 rows present, its 4 points inside every row,
 // unit x stride.
 __device__ __forceinline__ bool whole_block(const BlockView& v) {
@@ -145,7 +157,25 @@ __device__ __forceinline__ bool whole_block(const BlockView& v) {
 // (repeating the last level, row or point), also without branches.
 template <bool VEC4, bool COH = false>
 __device__ __forceinline__ void gather(const float* __restrict__ src, const BlockView& v,
-                                       float* val) {
+                                       float* val, uint32_t vspan = 0) {
+  if (COH && vspan != 0 && whole_block(v)) {
+    const __amdgpu_buffer_rsrc_t rs = coh_rsrc(src, vspan);
+#pragma unroll
+    for (int dz = 0; dz < 4; dz++) {
+#pragma unroll
+      for (int dy = 0; dy < 4; dy++) {
+        const uint32_t off = (uint32_t)(4 * (v.rbase[dy] + dz * v.lstride + v.x0));
+        f32x4 f = __builtin_bit_cast(
+            f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kSystemScope));
+        float* o = val + 16 * dz + 4 * dy;
+        o[0] = f.x;
+        o[1] = f.y;
+        o[2] = f.z;
+        o[3] = f.w;
+      }
+    }
+    return;
+  }
   if (VEC4 && !COH && whole_block(v)) {
 #pragma unroll
     for (int dz = 0; dz < 4; dz++) {
@@ -180,7 +210,22 @@ __device__ __forceinline__ void gather(const float* __restrict__ src, const Bloc
 
 template <bool VEC4, bool COH = false>
 __device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView& v,
-                                        const float* val) {
+                                        const float* val, uint32_t vspan = 0) {
+  if (COH && vspan != 0 && whole_block(v)) {
+    const __amdgpu_buffer_rsrc_t rs = coh_rsrc(dst, vspan);
+#pragma unroll
+    for (int dz = 0; dz < 4; dz++) {
+#pragma unroll
+      for (int dy = 0; dy < 4; dy++) {
+        const float* o = val + 16 * dz + 4 * dy;
+        f32x4 f = {o[0], o[1], o[2], o[3]};
+        const uint32_t off = (uint32_t)(4 * (v.rbase[dy] + dz * v.lstride + v.x0));
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, f), rs, (int)off, 0,
+                                               kSystemScope);
+      }
+    }
+    return;
+  }
   if (VEC4 && !COH && whole_block(v)) {
 #pragma unroll
     for (int dz = 0; dz < 4; dz++) {
@@ -297,7 +342,8 @@ __device__ __forceinline__ int opaque(int x) {
 template <int RATE, bool VEC4, bool COH = false, class Geo>
 __device__ __forceinline__ void encode_tile(const Geo& geo, const float* __restrict__ src,
                                             uint64_t* __restrict__ out, int rate, int lane,
-                                            uint64_t* wlds, int32_t b0, int nact) {
+                                            uint64_t* wlds, int32_t b0, int nact,
+                                            uint32_t vspan = 0) {
   const int stride = lds_stride(RATE > 0 ? RATE : rate);
   uint64_t* slice = wlds + lane * stride;
   for (int i = 0; i < stride; i++) slice[i] = 0;
@@ -305,7 +351,7 @@ __device__ __forceinline__ void encode_tile(const Geo& geo, const float* __restr
     BlockView v;
     geo.locate_tile(b0, lane, nact, v);
     float val[64];
-    gather<VEC4, COH>(src, v, val);
+    gather<VEC4, COH>(src, v, val, vspan);
     encode_block<RATE>(val, slice, rate);
   }
   wave_sync_lds();
@@ -315,7 +361,8 @@ __device__ __forceinline__ void encode_tile(const Geo& geo, const float* __restr
 template <int RATE, bool VEC4, bool COH = false, class Geo>
 __device__ __forceinline__ void decode_tile(const Geo& geo, const uint64_t* __restrict__ in,
                                             float* __restrict__ dst, int rate, int lane,
-                                            uint64_t* wlds, int32_t b0, int nact) {
+                                            uint64_t* wlds, int32_t b0, int nact,
+                                            uint32_t vspan = 0) {
   const int stride = lds_stride(RATE > 0 ? RATE : rate);
   for (int i = (RATE > 0 ? RATE : rate); i < stride; i++) wlds[lane * stride + i] = 0;
   copy_tile<RATE, false, COH>(const_cast<uint64_t*>(in) + (int64_t)b0 * rate, wlds, lane, nact,
@@ -326,7 +373,7 @@ __device__ __forceinline__ void decode_tile(const Geo& geo, const uint64_t* __re
     decode_block<RATE>(wlds + opaque(lane) * stride, val, rate);
     BlockView v;
     geo.locate_tile(b0, lane, nact, v);
-    scatter<VEC4, COH>(dst, v, val);
+    scatter<VEC4, COH>(dst, v, val, vspan);
   }
 }
 
@@ -424,33 +471,41 @@ __device__ __forceinline__ int64_t dev_load64i(const int64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Every lane loaded the same descriptor word: make that explicit (scalar).
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ void serve_tile(const ServeDesc& q, int lane, uint64_t* wlds,
                                            int32_t tile) {
   RegularGeo geo{q.geo};
   const int32_t b0 = tile << 6;
   const int nact = q.nblocks - b0 < 64 ? q.nblocks - b0 : 64;
+  const uint32_t vspan = __builtin_amdgcn_readfirstlane(q.vspan);
   if (q.op == 0) {
-    const float* src = reinterpret_cast<const float*>(q.in);
+    const float* src = reinterpret_cast<const float*>(uniform64(q.in));
     uint64_t* out = reinterpret_cast<uint64_t*>(q.out);
     if (q.rate == 8)
-      encode_tile<8, false, true>(geo, src, out, 8, lane, wlds, b0, nact);
+      encode_tile<8, false, true>(geo, src, out, 8, lane, wlds, b0, nact, vspan);
     else if (q.rate == 16)
-      encode_tile<16, false, true>(geo, src, out, 16, lane, wlds, b0, nact);
+      encode_tile<16, false, true>(geo, src, out, 16, lane, wlds, b0, nact, vspan);
     else if (q.rate == 32)
-      encode_tile<32, false, true>(geo, src, out, 32, lane, wlds, b0, nact);
+      encode_tile<32, false, true>(geo, src, out, 32, lane, wlds, b0, nact, vspan);
     else
-      encode_tile<0, false, true>(geo, src, out, q.rate, lane, wlds, b0, nact);
+      encode_tile<0, false, true>(geo, src, out, q.rate, lane, wlds, b0, nact, vspan);
   } else {
     const uint64_t* in = reinterpret_cast<const uint64_t*>(q.in);
-    float* dst = reinterpret_cast<float*>(q.out);
+    float* dst = reinterpret_cast<float*>(uniform64(q.out));
     if (q.rate == 8)
-      decode_tile<8, false, true>(geo, in, dst, 8, lane, wlds, b0, nact);
+      decode_tile<8, false, true>(geo, in, dst, 8, lane, wlds, b0, nact, vspan);
     else if (q.rate == 16)
-      decode_tile<16, false, true>(geo, in, dst, 16, lane, wlds, b0, nact);
+      decode_tile<16, false, true>(geo, in, dst, 16, lane, wlds, b0, nact, vspan);
     else if (q.rate == 32)
-      decode_tile<32, false, true>(geo, in, dst, 32, lane, wlds, b0, nact);
+      decode_tile<32, false, true>(geo, in, dst, 32, lane, wlds, b0, nact, vspan);
     else
-      decode_tile<0, false, true>(geo, in, dst, q.rate, lane, wlds, b0, nact);
+      decode_tile<0, false, true>(geo, in, dst, q.rate, lane, wlds, b0, nact, vspan);
   }
 }
 
@@ -507,93 +562,121 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
   uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(32);
   uint64_t t_work = t_start;
   uint64_t cursor = sys_load(&d.ctl->oldest);
+  uint64_t pub = 0;
+  // descriptor of the request whose tiles this wavefront last claimed; it
+  // stays valid while the wavefront holds a claimed tile of that request (the
+  // slot is not reused before every tile of the request is done)
+  ServeDesc q;
+  uint32_t qtag = 0;
+  bool have_q = false;
+  // tiles in hand: [t_next, t_end) of request q in slot hslot; `held` of the
+  // run are coded but not yet counted done
+  int32_t t_next = 0, t_end = 0, held = 0, hslot = 0;
   for (;;) {
-    const uint64_t now = __builtin_amdgcn_s_memrealtime();
-    if (now - t_start > d.max_ticks) break;
-    const uint64_t pub = dev_load(&d.dctl->published);
-    if (cursor >= pub) {
-      if (dev_load(&d.dctl->stop) || now - t_work > d.idle_ticks) break;
-      __builtin_amdgcn_s_sleep(32);
+    if (t_next < t_end) {
+      serve_tile(q, opaque(lane), wlds, t_next);
+      wave_sync_lds();
+      t_next++;
+      held++;
+      if (t_next == t_end) {
+        // the run's output was written through to memory (system-coherent
+        // stores); wait until every store has completed before counting the
+        // run done, so no cache write-back is needed
+        wait_memory();
+        if (lane == 0) {
+          const uint64_t prev = __hip_atomic_fetch_add(d.done + hslot, (uint64_t)held,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if ((int32_t)(uint32_t)prev + held == q.ntiles)
+            __hip_atomic_store(d.done_flag + hslot, q.seq + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        held = 0;
+        t_work = __builtin_amdgcn_s_memrealtime();
+      }
       continue;
     }
+    const uint64_t now = __builtin_amdgcn_s_memrealtime();
+    if (now - t_start > d.max_ticks) break;
+    if (cursor >= pub) {
+      pub = dev_load(&d.dctl->published);
+      if (cursor >= pub) {
+        if (dev_load(&d.dctl->stop) || now - t_work > d.idle_ticks) break;
+        __builtin_amdgcn_s_sleep(32);
+        continue;
+      }
+    }
     const int slot = (int)(cursor % (uint64_t)d.cap);
-    // claim a tile (lane 0) with a fetch-add on the slot's counter, whose
-    // high half names the request it counts for; share the result
-    uint64_t got = ~uint64_t(0);  // (request tag << 32) | tile, or ~0 = none
+    const uint32_t want = (uint32_t)cursor;
+    const int32_t take = have_q && qtag == want ? q.per_claim : 1;
+    // claim a run of tiles (lane 0): a fetch-add on the slot's counter, whose
+    // high half names the request it counts for.  The run belongs to that
+    // request, which is this one or (the slot reused after this one finished)
+    // a later one, and is processed for it.  A counter still naming an older
+    // request is moved on to this one with an atomic max (tags only grow, so
+    // the max neither loses a later tag nor fights the fetch-adds of other
+    // wavefronts); the done counter first, so that no tile of this request
+    // can complete before its done counter is reset.
+    uint64_t got = 0;  // (request tag << 32) | first tile
     if (lane == 0) {
-      const uint32_t want = (uint32_t)cursor;
-      const int32_t ntiles = dev_load32(&d.ring_dev[slot].ntiles);
       for (;;) {
-        uint64_t c = __hip_atomic_load(d.claim + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t cseq = (uint32_t)(c >> 32), cnt = (uint32_t)c;
-        if (cseq != want) {
-          if ((int32_t)(cseq - want) > 0) break;  // slot reused: this request is done
-          // first visitor of this request: reset the done counter, then the claim counter
-          uint64_t dv = __hip_atomic_load(d.done + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if ((uint32_t)(dv >> 32) != want)
-            __hip_atomic_compare_exchange_strong(d.done + slot, &dv, (uint64_t)want << 32,
-                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-          wait_memory();  // the done counter is reset before tiles can be claimed
-          __hip_atomic_compare_exchange_strong(d.claim + slot, &c, (uint64_t)want << 32,
-                                               __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-          continue;
+        const uint64_t prev = __hip_atomic_fetch_add(d.claim + slot, (uint64_t)take,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t pseq = (uint32_t)(prev >> 32);
+        if ((int32_t)(pseq - want) >= 0) {
+          got = prev;
+          break;
         }
-        if ((int32_t)cnt >= ntiles) break;  // every tile already claimed
-        // the counter may have moved on to a later request since the load: the
-        // tile returned then belongs to that request and is processed for it
-        got = __hip_atomic_fetch_add(d.claim + slot, uint64_t(1), __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-        break;
+        __hip_atomic_fetch_max(d.done + slot, (uint64_t)want << 32, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        wait_memory();
+        __hip_atomic_fetch_max(d.claim + slot, (uint64_t)want << 32, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        wait_memory();
       }
     }
     got = __shfl(got, 0, 64);
-    if (got == ~uint64_t(0)) {
-      cursor++;
-      continue;
-    }
-    const uint32_t gseq = (uint32_t)(got >> 32);
+    const uint32_t gtag = (uint32_t)(got >> 32);
     const int32_t tile = (int32_t)(uint32_t)got;
-    const ServeDesc* r = d.ring_dev + slot;
-    ServeDesc q;
-    q.seq = dev_load(&r->seq);
-    q.ntiles = dev_load32(&r->ntiles);
-    if ((uint32_t)q.seq != gseq || tile >= q.ntiles) {
-      // overshoot past the last tile (or a slot reused twice meanwhile): nothing to do
-      if ((uint32_t)q.seq == (uint32_t)cursor) continue;
+    if (!have_q || qtag != gtag) {
+      const ServeDesc* r = d.ring_dev + slot;
+      // coherent vector loads, kept in scalar registers (every lane read the
+      // same words)
+      q.seq = uniform64(dev_load(&r->seq));
+      q.ntiles = __builtin_amdgcn_readfirstlane(dev_load32(&r->ntiles));
+      q.op = __builtin_amdgcn_readfirstlane(dev_load32(&r->op));
+      q.rate = __builtin_amdgcn_readfirstlane(dev_load32(&r->rate));
+      q.nblocks = __builtin_amdgcn_readfirstlane(dev_load32(&r->nblocks));
+      q.vspan = (uint32_t)__builtin_amdgcn_readfirstlane(
+          dev_load32(reinterpret_cast<const int32_t*>(&r->vspan)));
+      q.per_claim = __builtin_amdgcn_readfirstlane(dev_load32(&r->per_claim));
+      q.geo.nx = (int64_t)uniform64((uint64_t)dev_load64i(&r->geo.nx));
+      q.geo.ny = (int64_t)uniform64((uint64_t)dev_load64i(&r->geo.ny));
+      q.geo.nz = (int64_t)uniform64((uint64_t)dev_load64i(&r->geo.nz));
+      q.geo.sx = (int64_t)uniform64((uint64_t)dev_load64i(&r->geo.sx));
+      q.geo.sy = (int64_t)uniform64((uint64_t)dev_load64i(&r->geo.sy));
+      q.geo.sz = (int64_t)uniform64((uint64_t)dev_load64i(&r->geo.sz));
+      q.geo.nbx = __builtin_amdgcn_readfirstlane(dev_load32(&r->geo.nbx));
+      q.geo.nby = __builtin_amdgcn_readfirstlane(dev_load32(&r->geo.nby));
+      q.in = uniform64(dev_load(&r->in));
+      q.out = uniform64(dev_load(&r->out));
+      qtag = gtag;
+      have_q = (uint32_t)q.seq == gtag;
+      if (!have_q) {
+        // the request finished and the slot already holds the next one's
+        // descriptor (its claim counter not reset yet): nothing to do here
+        cursor++;
+        continue;
+      }
+    }
+    if (tile >= q.ntiles) {
+      // every tile of the slot's request is claimed (and the cursor's request
+      // with it): move on
       cursor++;
       continue;
     }
-    q.op = dev_load32(&r->op);
-    q.rate = dev_load32(&r->rate);
-    q.nblocks = dev_load32(&r->nblocks);
-    q.vec4 = dev_load32(&r->vec4);
-    q.pad = 0;
-    q.geo.nx = dev_load64i(&r->geo.nx);
-    q.geo.ny = dev_load64i(&r->geo.ny);
-    q.geo.nz = dev_load64i(&r->geo.nz);
-    q.geo.sx = dev_load64i(&r->geo.sx);
-    q.geo.sy = dev_load64i(&r->geo.sy);
-    q.geo.sz = dev_load64i(&r->geo.sz);
-    q.geo.nbx = dev_load32(&r->geo.nbx);
-    q.geo.nby = dev_load32(&r->geo.nby);
-    q.in = dev_load(&r->in);
-    q.out = dev_load(&r->out);
-    serve_tile(q, opaque(lane), wlds, tile);
-    wave_sync_lds();
-    // the tile's output was written through to memory (system-coherent
-    // stores); wait until every store of the wavefront has completed before
-    // counting the tile done, so no cache write-back is needed
-    wait_memory();
-    if (lane == 0) {
-      uint64_t prev = __hip_atomic_fetch_add(d.done + slot, 1, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-      if ((int32_t)(uint32_t)prev + 1 == q.ntiles)
-        __hip_atomic_store(d.done_flag + slot, q.seq + 1, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-    t_work = __builtin_amdgcn_s_memrealtime();
+    t_next = tile;
+    t_end = q.ntiles - tile < take ? q.ntiles : tile + take;
+    hslot = slot;
   }
 }
 

@@ -13,6 +13,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <deque>
@@ -69,9 +70,18 @@ bool request_ok(const zfpx_request* rq, int64_t* nblocks, size_t* bytes) {
   return true;
 }
 
-bool vec4_ok(const zfpx_request* rq) {
+// Byte span of the request's float32 array when the device loop may move it
+// in 16-byte pieces through a 32-bit offset (unit x stride, rows 16-byte
+// aligned, non-negative strides, span below 4 GiB); 0 otherwise.
+uint32_t vector_span(const zfpx_request* rq) {
   const void* f = rq->op == 0 ? rq->d_in : rq->d_out;
-  return rq->sx == 1 && (rq->sy & 3) == 0 && (rq->sz & 3) == 0 && ((uintptr_t)f & 15) == 0;
+  if (rq->sx != 1 || (rq->sy & 3) != 0 || (rq->sz & 3) != 0 || ((uintptr_t)f & 15) != 0)
+    return 0;
+  if (rq->sy < 0 || rq->sz < 0) return 0;
+  const int64_t last = (rq->nx - 1) + (rq->ny - 1) * rq->sy + (rq->nz - 1) * rq->sz;
+  const int64_t bytes = 4 * (last + 1);
+  if (bytes <= 0 || bytes > 0xffffffffLL) return 0;
+  return (uint32_t)bytes;
 }
 
 }  // namespace
@@ -179,7 +189,10 @@ static int progress_locked(zfpx_server* sv) {
     q.rate = p.rq.rate;
     q.nblocks = (int32_t)p.nblocks;
     q.ntiles = (int32_t)((p.nblocks + 63) / 64);
-    q.vec4 = vec4_ok(&p.rq) ? 1 : 0;
+    q.vspan = vector_span(&p.rq);
+    // large requests hand out tiles in runs (fewer counter atomics); a run of
+    // one keeps smaller requests spread over as many wavefronts as possible
+    q.per_claim = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, q.ntiles / 512));
     q.geo = RegularDev{p.rq.nx, p.rq.ny, p.rq.nz, p.rq.sx, p.rq.sy, p.rq.sz,
                        (int32_t)ceil4(p.rq.nx), (int32_t)ceil4(p.rq.ny)};
     q.in = (uint64_t)(uintptr_t)p.rq.d_in;
@@ -220,7 +233,9 @@ int zfpx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t workg
     delete sv;
     return ZFPX_EHIP;
   }
-  sv->workgroups = workgroups > 0 ? workgroups : device_cu_count() * 4;
+  // two workgroups (four wavefronts) per compute unit: more wavefronts only
+  // add contention on the claim counters
+  sv->workgroups = workgroups > 0 ? workgroups : device_cu_count() * 2;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, sv->device) != hipSuccess ||
       khz <= 0)
@@ -261,8 +276,9 @@ int zfpx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t workg
       return ZFPX_EHIP;
     }
   }
-  // tag every slot with a request number that precedes any real one
-  std::vector<uint64_t> init(max_slots, (uint64_t)0xffffffffu << 32);
+  // claim and done counters: (request number << 32) | count, all starting
+  // at request 0 with count 0 (later requests move them on with an atomic max)
+  std::vector<uint64_t> init(max_slots, 0);
   if (hipMemcpy(sv->claim, init.data(), sizeof(uint64_t) * max_slots, hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(sv->done, init.data(), sizeof(uint64_t) * max_slots, hipMemcpyHostToDevice) !=
@@ -282,6 +298,8 @@ int zfpx_server_submit(zfpx_server* sv, const zfpx_request* rq, uint64_t* ticket
   size_t bytes;
   if (!request_ok(rq, &nb, &bytes) || bytes > sv->budget) return ZFPX_EINVAL;
   std::lock_guard<std::mutex> g(sv->mu);
+  // request numbers tag the device counters in 32 bits and must not wrap
+  if (sv->next_seq + sv->queue.size() >= 0xffffffffULL) return ZFPX_ESTATE;
   if (sv->queue.size() >= sv->max_queue) return ZFPX_EAGAIN;
   Pending p{sv->next_ticket++, *rq, nb, bytes, now_s()};
   *ticket = p.ticket;
