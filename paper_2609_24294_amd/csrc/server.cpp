@@ -110,6 +110,13 @@ struct zfpx_server {
   std::deque<Pending> queue;
   std::vector<SlotState> slots;
   std::unordered_map<uint64_t, Result> results;
+  // requests low_seq .. next_seq-1 may be in flight (at most cap of them)
+  uint64_t low_seq = 0;
+  size_t nactive = 0;
+  double last_query = 0;  // last time the device loop's end was queried
+  // tickets completed since the last look, gathered while collect_done is set
+  bool collect_done = false;
+  std::vector<uint64_t> completed;
   uint64_t idle_ticks = 0, max_ticks = 0;
   int device = 0;
 };
@@ -133,10 +140,13 @@ static void server_free(zfpx_server* sv) {
 
 // Launch the device loop if requests are in flight and none is running.
 static int ensure_loop(zfpx_server* sv) {
-  bool any = false;
-  for (const SlotState& s : sv->slots) any |= s.active;
-  if (!any) return ZFPX_OK;
+  if (sv->nactive == 0) return ZFPX_OK;
   if (sv->loop_running) {
+    // the loop leaves only after an idle spell: asking the runtime at every
+    // host pass would cost more than it tells
+    const double t = now_s();
+    if (t - sv->last_query < 20e-6) return ZFPX_OK;
+    sv->last_query = t;
     hipError_t q = hipEventQuery(sv->loop_done);
     if (q == hipErrorNotReady) return ZFPX_OK;
     if (q != hipSuccess) return ZFPX_EHIP;
@@ -164,21 +174,27 @@ static int ensure_loop(zfpx_server* sv) {
 // Collect completions, admit queued requests, keep the loop running.
 static int progress_locked(zfpx_server* sv) {
   const double t = now_s();
-  uint64_t oldest = sv->next_seq;
-  for (int j = 0; j < sv->cap; j++) {
+  for (uint64_t sq = sv->low_seq; sq < sv->next_seq; sq++) {
+    const int j = (int)(sq % (uint64_t)sv->cap);
     SlotState& s = sv->slots[j];
-    if (!s.active) continue;
+    if (!s.active || s.seq != sq) continue;
     uint64_t f = __atomic_load_n(&sv->flags[j], __ATOMIC_ACQUIRE);
     if (f == s.seq + 1) {
       s.active = false;
+      sv->nactive--;
       sv->inflight -= s.bytes;
       Result& r = sv->results[s.ticket];
       r.done = true;
       r.latency = t - s.t_submit;
-    } else if (s.seq < oldest) {
-      oldest = s.seq;
+      if (sv->collect_done) sv->completed.push_back(s.ticket);
     }
   }
+  while (sv->low_seq < sv->next_seq) {
+    const SlotState& s = sv->slots[sv->low_seq % (uint64_t)sv->cap];
+    if (s.active && s.seq == sv->low_seq) break;
+    sv->low_seq++;
+  }
+  uint64_t oldest = sv->low_seq;
   while (!sv->queue.empty()) {
     Pending& p = sv->queue.front();
     int j = (int)(sv->next_seq % (uint64_t)sv->cap);
@@ -200,6 +216,7 @@ static int progress_locked(zfpx_server* sv) {
     memcpy(&sv->ring[j], &q, sizeof q);
     SlotState& s = sv->slots[j];
     s.active = true;
+    sv->nactive++;
     s.seq = q.seq;
     s.ticket = p.ticket;
     s.bytes = p.bytes;
@@ -335,9 +352,7 @@ int zfpx_server_drain(zfpx_server* sv, double timeout_s) {
       std::lock_guard<std::mutex> g(sv->mu);
       int st = progress_locked(sv);
       if (st) return st;
-      bool any = !sv->queue.empty();
-      for (const SlotState& s : sv->slots) any |= s.active;
-      if (!any) return ZFPX_OK;
+      if (sv->queue.empty() && sv->nactive == 0) return ZFPX_OK;
     }
     if (now_s() > t_end) return ZFPX_EAGAIN;
     std::this_thread::yield();
@@ -382,19 +397,23 @@ int zfpx_server_replay(zfpx_server* sv, const zfpx_request* rq, const double* ar
         sv->queue.push_back(p);
         next++;
       }
+      sv->collect_done = true;
       int st = progress_locked(sv);
-      if (st) return st;
-      for (auto it = index.begin(); it != index.end();) {
-        auto r = sv->results.find(it->first);
-        if (r != sv->results.end() && r->second.done) {
-          latency_s[it->second] = r->second.latency;
-          sv->results.erase(r);
-          it = index.erase(it);
-          finished++;
-        } else {
-          ++it;
-        }
+      sv->collect_done = false;
+      if (st) {
+        sv->completed.clear();
+        return st;
       }
+      for (uint64_t tk : sv->completed) {
+        auto it = index.find(tk);
+        if (it == index.end()) continue;  // a request submitted outside the replay
+        auto r = sv->results.find(tk);
+        latency_s[it->second] = r->second.latency;
+        sv->results.erase(r);
+        index.erase(it);
+        finished++;
+      }
+      sv->completed.clear();
     }
   }
   return ZFPX_OK;

@@ -121,3 +121,46 @@ def test_replay_forms_agree(zfpx_lib):
     torch.cuda.synchronize()
     assert (lat2 > 0).all()
     _check(outs, refs)
+
+
+def test_server_large_requests_in_runs(zfpx_lib):
+    """Requests of 1024+ tiles are handed out in runs of several tiles per
+    claim (the last run of a request cut short); mixed with small requests,
+    every result still equals its one-launch form."""
+    rng = np.random.default_rng(43)
+    pool = torch.from_numpy(W.serving_pool(nx_max=32768)).to(DEV)
+    reqs, outs, refs = [], [], []
+    for i, nx in enumerate([32764, 12, 16384, 300, 32768, 4, 20001, 64]):
+        view = pool[:, :, :nx]
+        rate = int(rng.choice([8, 16, 32]))
+        words = zfpx_lib.zfpx_encode_fixed_rate(view, rate)
+        if i % 2 == 0:
+            out = torch.zeros_like(words)
+            reqs.append(zfpx_lib.make_request(0, rate, view, out, tag=i))
+            outs.append(out)
+            refs.append(words)
+        else:
+            arr = torch.full(view.shape, -7.0, device=DEV)
+            ref = torch.full(view.shape, -7.0, device=DEV)
+            zfpx_lib.zfpx_decode_fixed_rate(words, rate, ref)
+            reqs.append(zfpx_lib.make_request(1, rate, arr, words, tag=i))
+            outs.append((arr, words))  # requests hold raw pointers: keep inputs alive
+            refs.append(ref)
+        # decoding the large ones too (runs on the decode path)
+        if nx >= 16384:
+            arr = torch.full(view.shape, -7.0, device=DEV)
+            ref = torch.full(view.shape, -7.0, device=DEV)
+            zfpx_lib.zfpx_decode_fixed_rate(words, rate, ref)
+            reqs.append(zfpx_lib.make_request(1, rate, arr, words, tag=100 + i))
+            outs.append((arr, words))
+            refs.append(ref)
+    torch.cuda.synchronize()
+    tiles = [-(-(-(-rq.nx // 4) * -(-rq.ny // 4) * -(-rq.nz // 4)) // 64) for rq in reqs]
+    assert max(tiles) >= 4096 and any(t >= 1024 and t % 8 for t in tiles)
+    sv = zfpx_lib.Server(64 << 30, max_slots=8)
+    for rq in reqs:
+        sv.submit(rq)
+    sv.drain(60.0)
+    sv.close()
+    torch.cuda.synchronize()
+    _check(outs, refs)
