@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batched vs per-chunk comparison (lambda->theta buffer)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the O2560 x 90 levels (9.47 GB) throughput leg")
     ap.add_argument("--serving-requests", type=int, default=10000)
     return ap.parse_args()
 
@@ -195,11 +197,19 @@ def main():
     if not args.no_accuracy:
         accuracy = accuracy_report(plan, src[0], dst[0], nvals, nblocks, torch, zfpx, W)
 
+    large = None
+    if not args.no_large:
+        del src, dst, send
+        torch.cuda.empty_cache()
+        large = large_report(torch, zfpx, W)
+        src = dst = send = None
+
     batching = None
     if not args.no_batching:
         del src, dst, send
         torch.cuda.empty_cache()
         batching = batching_report(torch, zfpx, W)
+        src = dst = send = None
 
     serving = None
     if not args.no_serving:
@@ -243,6 +253,7 @@ def main():
         "cpu_baseline": cpu,
         **extras,
         "accuracy": accuracy,
+        "large": large,
         "batching": batching,
         "serving": serving,
     }
@@ -281,6 +292,50 @@ def accuracy_report(plan, src, dst, nvals, nblocks, torch, zfpx, W):
     x32 = src.cpu().numpy().reshape(shape)
     out["float32_storage"] = {names[f]: float(f"{metrics.error_report(x64[f], x32[f], False)['block_mean']:.3e}")
                               for f in range(4)}
+    return out
+
+
+def large_report(torch, zfpx, W, reps=5):
+    """Large single-GPU throughput: one float32 field on the O2560 reduced grid
+    x 90 levels (9.47 GB, one chunk), encode and decode at rates 8 and 16,
+    each against the HBM roofline."""
+    log("large: generating 8 levels of the O2560 field")
+    base = W.large_field_levels(8)
+    cs = W.large_chunkset()
+    plan = zfpx.Plan.from_chunkset(cs)
+    dev = torch.device("cuda:0")
+    npts = base.shape[1]
+    nlev = cs.buffer_elems // npts
+    b = torch.from_numpy(base.reshape(-1)).to(dev)
+    del base
+    src = torch.empty(cs.buffer_elems, dtype=torch.float32, device=dev)
+    for k in range(0, nlev, 8):  # level k repeats level k % 8
+        n = min(8, nlev - k) * npts
+        src[k * npts: k * npts + n] = b[:n]
+    del b
+    dst = torch.empty_like(src)
+    in_bytes = 4 * plan.nvalues
+    out = {"workload": f"O2560 reduced grid ({npts} points/level) x {nlev} levels f32 "
+                       f"({in_bytes / 1e9:.2f} GB), one chunk",
+           "blocks": plan.nblocks,
+           "data": "levels 8..89 repeat generated levels 0..7 (no 4-level block straddles a repeat)"}
+    for rate in (8, 16):
+        send = torch.empty(plan.nblocks * rate, dtype=torch.int64, device=dev)
+        enc = lambda i: zfpx.zfpx_pack_encode(plan, src, rate, send)
+        dec = lambda i: zfpx.zfpx_decode_unpack(plan, send, rate, dst)
+        log(f"large: rate {rate}")
+        _, (te, td) = timed_loop([enc, dec], reps, 1, torch)
+        alg = in_bytes + plan.nblocks * 8 * rate
+        out[f"rate{rate}"] = {
+            "encode_ms": round(te, 3), "decode_ms": round(td, 3),
+            "encode_gbs": round(alg / (te * 1e-3) / 1e9, 1),
+            "decode_gbs": round(alg / (td * 1e-3) / 1e9, 1),
+            "encode_hbm_frac": round(alg / (te * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "decode_hbm_frac": round(alg / (td * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes": alg}
+        del send
+    del src, dst
+    torch.cuda.empty_cache()
     return out
 
 

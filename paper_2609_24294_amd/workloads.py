@@ -383,6 +383,25 @@ def large_field(L: int = 42):
     return reduced_grid_field(LARGE["n_half"], LARGE["nlev"], 4, L)
 
 
+def large_field_levels(nmade: int = 8, L: int = 42):
+    """The first `nmade` levels (a multiple of 4) of the O2560 x 90 field.
+
+    Generating all 90 levels takes minutes on the host; the large buffer is
+    built by repeating these levels in order (see large_field_repeated), and
+    since a 4x4x4 block spans 4 levels starting at a multiple of 4, no block
+    straddles a repeat: every block has the generator's level-to-level
+    statistics.
+    """
+    assert nmade % 4 == 0
+    return reduced_grid_field(LARGE["n_half"], nmade, 4, L)
+
+
+def large_field_repeated(levels: np.ndarray, nlev: int = LARGE["nlev"]) -> np.ndarray:
+    """[nlev, points] float32: level k is levels[k % len(levels)]."""
+    reps = -(-nlev // levels.shape[0])
+    return np.ascontiguousarray(np.tile(levels, (reps, 1))[:nlev])
+
+
 # ---------------------------------------------------------------------------
 # Serving request stream
 # ---------------------------------------------------------------------------

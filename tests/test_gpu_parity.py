@@ -242,6 +242,18 @@ def test_empty_inputs(zfpx_lib):
     assert send.numel() == 0
 
 
+def test_large_full_size_sampled(zfpx_lib):
+    """O2560 x 90 levels (9.47 GB, one chunk, 37,859,840 blocks): full-size
+    launches, sampled blocks against the oracle.  Levels 8..89 repeat 0..7."""
+    cs = W.large_chunkset()
+    x32 = W.large_field_repeated(W.large_field_levels(8))
+    assert x32.size == cs.buffer_elems == 2367590400
+    plan = _check_plan(zfpx_lib, cs, x32, (8, 16), full=False, sample=2000, seed=13)
+    assert plan.nblocks == 37859840
+    _, _, total = plan.sizes(8)
+    assert total == 37859840 * 64
+
+
 def test_ltheta_full_size_sampled(zfpx_lib):
     cs = W.ltheta_chunkset()
     x32 = W.ltheta_field()
