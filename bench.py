@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+VALU_SIMD_CYCLES_PER_S = 1024 * 2.4e9  # 256 CUs x 4 SIMDs at 2.4 GHz
 
 
 KERNEL_SOURCES = ("paper_2609_24294_amd/csrc/kernels.hip",
@@ -51,7 +52,7 @@ def measured_traffic(kernel: str, rate: int):
             return None
         k = block["kernels"][kernel][str(rate)]
         return {"bytes": k["read_bytes"] + k["write_bytes"], "read": k["read_bytes"],
-                "write": k["write_bytes"]}
+                "write": k["write_bytes"], "valu": k.get("valu_insts")}
     except (OSError, IndexError, KeyError, ValueError):
         return None
 
@@ -249,7 +250,13 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "algorithmic_bytes": alg_dom,
                      "traffic": traffic["bytes"] if traffic else None,
-                     "traffic_read_write": [traffic["read"], traffic["write"]] if traffic else None},
+                     "traffic_read_write": [traffic["read"], traffic["write"]] if traffic else None,
+                     # the same kernel against its instruction-issue ceiling: VALU
+                     # wavefront instructions (counter pass) x 4 cycles each on a
+                     # 16-lane SIMD, over 1024 SIMDs x 2.4 GHz x the launch time
+                     "valu_issue_frac": (round(traffic["valu"] * 4 / (VALU_SIMD_CYCLES_PER_S
+                                                                     * t_dom * 1e-3), 4)
+                                         if traffic and traffic["valu"] else None)},
         "cpu_baseline": cpu,
         **extras,
         "accuracy": accuracy,

@@ -193,7 +193,7 @@ int zfpx_decode_unpack_chunks(const zfpx_plan* plan, int32_t first, int32_t coun
  * zfpx_plan_set_config stores it in the plan for that op and rate (rate 0 =
  * every rate without an entry of its own); it is then used by every launch
  * on that plan.  Returns EINVAL for an unsupported configuration.  Without
- * an entry a launch uses 64 threads and one tile per wavefront.
+ * an entry a launch uses 128 threads and one tile per wavefront.
  */
 int zfpx_plan_set_config(zfpx_plan* plan, int op, int rate, int wg_threads, int grid_wgs);
 int zfpx_plan_get_config(const zfpx_plan* plan, int op, int rate, int* wg_threads,

@@ -25,12 +25,11 @@ bool rate_ok(int rate) { return rate >= 1 && rate <= 32; }
 int64_t ceil4(int64_t n) { return (n + 3) / 4; }
 bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 
-// One wavefront per workgroup: a finished wavefront frees its slot at once
-// instead of waiting for the slowest wavefront of its workgroup (coding time
-// varies from tile to tile).
+// One tile per wavefront, two wavefronts per workgroup (timed on the z->lambda
+// share with encode and decode alternating: 64 threads lose 5% and 256 match).
 LaunchCfg default_cfg(int) {
   LaunchCfg c;
-  c.wg = 64;
+  c.wg = 128;
   c.grid = 0;
   return c;
 }
@@ -60,7 +59,7 @@ struct zfpx_plan {
     if (it != cfg.end()) return it->second;
     it = cfg.find({op, 0});
     if (it != cfg.end() && lds_bytes(it->second.wg, rate) <= device_max_lds()) return it->second;
-    return default_cfg(rate);
+    return default_cfg(op);
   }
 };
 
@@ -124,7 +123,7 @@ int zfpx_encode_fixed_rate(const float* d_in, int64_t nx, int64_t ny, int64_t nz
   if (!d_in || !d_out || !aligned(d_out, 8)) return ZFPX_EINVAL;
   if ((int64_t)out_bytes < nb * 8 * rate) return ZFPX_ENOSPC;
   hipError_t e = launch_regular_encode(g, regular_vec4(d_in, sx, sy, sz), d_in, (uint64_t*)d_out,
-                                       rate, (int32_t)nb, default_cfg(rate), (hipStream_t)stream);
+                                       rate, (int32_t)nb, default_cfg(kOpEncode), (hipStream_t)stream);
   return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
 }
 
@@ -139,7 +138,7 @@ int zfpx_decode_fixed_rate(const void* d_in, size_t in_bytes, int64_t nx, int64_
   if (!d_in || !d_out || !aligned(d_in, 8)) return ZFPX_EINVAL;
   if ((int64_t)in_bytes < nb * 8 * rate) return ZFPX_ENOSPC;
   hipError_t e = launch_regular_decode(g, regular_vec4(d_out, sx, sy, sz), (const uint64_t*)d_in,
-                                       d_out, rate, (int32_t)nb, default_cfg(rate),
+                                       d_out, rate, (int32_t)nb, default_cfg(kOpDecode),
                                        (hipStream_t)stream);
   return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
 }
@@ -454,7 +453,7 @@ int zfpx_autotune(zfpx_plan* p, int op, int rate, const float* d_src, int64_t sr
   }
   auto saved = p->cfg;
   double best = 1e300;
-  LaunchCfg best_c = default_cfg(rate);
+  LaunchCfg best_c = default_cfg(op);
   int st = ZFPX_OK;
   for (const LaunchCfg& c : cands) {
     p->cfg[{op, rate}] = c;

@@ -264,21 +264,6 @@ ZFPX_HD uint64_t window64(const uint64_t* s, uint32_t pos) {
   return (a >> b) | ((c << 1) << (63 - b));
 }
 
-// Marks v as used here (device code): its load is issued before this point
-// instead of being sunk into a later branch.
-ZFPX_HD void issue_now(uint64_t v) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  asm volatile("" ::"v"(v));
-#else
-  (void)v;
-#endif
-}
-
-// Bits b .. b+63 of the 128-bit value (hi:lo), b in [0, 63].
-ZFPX_HD uint64_t funnel64(uint64_t lo, uint64_t hi, uint32_t b) {
-  return (lo >> b) | ((hi << 1) << (63 - b));
-}
-
 // ---------------------------------------------------------------------------
 // Encoder
 // ---------------------------------------------------------------------------
@@ -386,13 +371,8 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt) {
   for (int k = 31; k >= 0; k--) {
     uint64_t x = 0;
     if (pos < maxbits) {
-      // the three words holding the plane's first 128 bits (up to word
-      // rate + 1, inside the zero slack), read together up front
-      const uint32_t wi = pos >> 6, b = pos & 63;
-      const uint64_t w0 = in[wi], w1 = in[wi + 1], w2 = in[wi + 2];
       int m = (int)(maxbits - pos) < n ? (int)(maxbits - pos) : n;
-      x = funnel64(w0, w1, b) & low_mask(m);  // the first n bits verbatim
-      issue_now(w2);  // one LDS round trip per plane, not two
+      x = window64(in, pos) & low_mask(m);  // the first n bits verbatim
       pos += m;
       if (n < 64 && pos < maxbits) {
         // Common case first: every group test and scan of the plane lies in
@@ -400,8 +380,7 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt) {
         // coefficient 63 (whose one would be implied).  Otherwise the plane
         // is decoded group by group from the same state.
         bool done = false;
-        const uint32_t e = b + (uint32_t)m;  // window start, bits past word wi
-        uint64_t s = e >= 64 ? funnel64(w1, w2, e - 64) : funnel64(w0, w1, e);
+        uint64_t s = window64(in, pos);
         uint64_t y = 0;
         int c = 0, used = 1;  // coefficients and bits taken; the closing zero
         while (s & 1) {

@@ -37,7 +37,7 @@ struct RegularDev {
 // Launch configuration: threads per workgroup and persistent grid (0 = one
 // 64-block tile per wavefront).
 struct LaunchCfg {
-  int wg = 64;
+  int wg = 128;
   int grid = 0;
 };
 
