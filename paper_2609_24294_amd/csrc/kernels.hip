@@ -680,7 +680,7 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
   }
 }
 
-// float16 comparator: 8 values per thread per step when aligned.
+// float16 comparator; unaligned buffers take one value per thread.
 __global__ __launch_bounds__(256) void k_f16_truncate_v8(const float4* __restrict__ in,
                                                          size_t n8, uint4* __restrict__ out) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8;
@@ -703,14 +703,21 @@ __global__ __launch_bounds__(256) void k_f16_truncate_s(const float* __restrict_
     out[i] = __builtin_bit_cast(uint16_t, (_Float16)in[i]);
 }
 
-__global__ __launch_bounds__(256) void k_f16_restore_v8(const uint4* __restrict__ in, size_t n8,
+// Restore: groups of 4 values (one 8-byte load, one 16-byte store); each
+// thread takes four groups a whole grid apart, so four loads are in flight.
+__global__ __launch_bounds__(256) void k_f16_restore_v4(const uint2* __restrict__ in, size_t n4,
                                                         float4* __restrict__ out) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8;
-       i += (size_t)gridDim.x * blockDim.x) {
-    uint4 r = in[i];
-    auto f = [](uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)w); };
-    out[2 * i] = make_float4(f(r.x), f(r.x >> 16), f(r.y), f(r.y >> 16));
-    out[2 * i + 1] = make_float4(f(r.z), f(r.z >> 16), f(r.w), f(r.w >> 16));
+  const size_t T = (size_t)gridDim.x * blockDim.x;
+  auto f = [](uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)w); };
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += 4 * T) {
+    uint2 r[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (i + k * T < n4) r[k] = in[i + k * T];
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (i + k * T < n4)
+        out[i + k * T] = make_float4(f(r[k].x), f(r[k].x >> 16), f(r[k].y), f(r[k].y >> 16));
   }
 }
 
@@ -884,11 +891,11 @@ hipError_t launch_f16_truncate(const float* in, size_t n, uint16_t* out, hipStre
 hipError_t launch_f16_restore(const uint16_t* in, size_t n, float* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
   size_t done = 0;
-  if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0 && n >= 8) {
-    size_t n8 = n / 8;
-    hipLaunchKernelGGL(k_f16_restore_v8, dim3(elementwise_grid(n8)), dim3(256), 0, s,
-                       reinterpret_cast<const uint4*>(in), n8, reinterpret_cast<float4*>(out));
-    done = n8 * 8;
+  if (((uintptr_t)in & 7) == 0 && ((uintptr_t)out & 15) == 0 && n >= 4) {
+    size_t n4 = n / 4;
+    hipLaunchKernelGGL(k_f16_restore_v4, dim3(elementwise_grid((n4 + 3) / 4)), dim3(256), 0, s,
+                       reinterpret_cast<const uint2*>(in), n4, reinterpret_cast<float4*>(out));
+    done = n4 * 4;
   }
   if (done < n)
     hipLaunchKernelGGL(k_f16_restore_s, dim3(elementwise_grid(n - done)), dim3(256), 0, s,

@@ -212,9 +212,10 @@ def test_f16_matches_numpy(zfpx_lib):
                          1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11, np.inf, -np.inf], np.float32)
     bits = rng.integers(0, 2 ** 32, 300000, dtype=np.uint64).astype(np.uint32).view(np.float32)
     x = np.concatenate([specials, bits, (280 + 15 * rng.standard_normal(100003)).astype(np.float32)])
-    for off in (0, 1, 3):  # aligned and unaligned starts, ragged tails
+    dall = torch.from_numpy(x).to(DEV)
+    for off in (0, 1, 3):  # aligned and unaligned device starts, ragged tails
         xs = x[off:]
-        d = torch.from_numpy(xs.copy()).to(DEV)
+        d = dall[off:]  # a view: off > 0 is not 16-byte aligned (element-wise path)
         h = zfpx_lib.f16_truncate(d)
         want = oracle.f16_truncate(xs)
         got = h.cpu().numpy().view(np.uint16)
@@ -222,6 +223,10 @@ def test_f16_matches_numpy(zfpx_lib):
         assert np.array_equal(got[~nan], want[~nan])
         assert np.isnan(got[nan].view(np.float16)).all()
         back = zfpx_lib.f16_restore(h)
+        hv = torch.empty(h.numel() + 1, dtype=h.dtype, device=DEV)
+        hv[1:] = h  # an unaligned float16 input as well
+        back2 = zfpx_lib.f16_restore(hv[1:])
+        assert torch.equal(back2.view(torch.int32), back.view(torch.int32))  # NaNs too
         wantb = oracle.f16_restore(want)
         gb = back.cpu().numpy()
         assert np.array_equal(f32bits(gb[~nan]), f32bits(wantb[~nan]))
