@@ -384,15 +384,14 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt) {
         uint64_t y = 0;
         int c = 0, used = 1;  // coefficients and bits taken; the closing zero
         while (s & 1) {
-          uint64_t r = s >> 1;
-          // no one left in the window: t = 64 ends the loop and fails the
-          // window test below
-          int t = r != 0 ? ctz64(r) : 64;
+          uint64_t r = s >> 1;  // bit 63 clear
+          // with bit 63 set, t = 63 means no one was left in the window: the
+          // window test below then fails (used > 64), and s becomes 0
+          int t = ctz64(r | (uint64_t(1) << 63));
           y |= uint64_t(1) << ((c + t) & 63);
           c += t + 1;
           used += t + 2;
-          s = (r >> (t & 63)) >> 1;
-          if (t == 64) s = 0;
+          s = (r >> t) >> 1;
         }
         if (used <= 64 && pos + used <= maxbits && n + c <= 63) {
           x |= y << n;
