@@ -104,12 +104,19 @@ ZFPX_HD void lift_fwd(int32_t& x0, int32_t& x1, int32_t& x2, int32_t& x3) {
 
 ZFPX_HD void lift_inv(int32_t& x0, int32_t& x1, int32_t& x2, int32_t& x3) {
   auto add = [](int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); };
-  auto dbl_sub = [](int32_t a, int32_t b) { return (int32_t)(((uint32_t)a << 1) - (uint32_t)b); };
-  x1 = add(x1, x3 >> 1); x3 = (int32_t)((uint32_t)x3 - (uint32_t)(x1 >> 1));
-  x1 = add(x1, x3); x3 = dbl_sub(x3, x1);
-  x2 = add(x2, x0); x0 = dbl_sub(x0, x2);
-  x1 = add(x1, x2); x2 = dbl_sub(x2, x1);
-  x3 = add(x3, x0); x0 = dbl_sub(x0, x3);
+  auto sub = [](int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); };
+  // The steps "a += b; b = 2b - a" leave b = 2b - (a + b) = b - a (mod 2^32):
+  // two operations instead of three.
+  auto step = [&](int32_t& a, int32_t& b) {
+    const int32_t a0 = a;
+    a = add(a0, b);
+    b = sub(b, a0);
+  };
+  x1 = add(x1, x3 >> 1); x3 = sub(x3, x1 >> 1);
+  step(x1, x3);
+  step(x2, x0);
+  step(x1, x2);
+  step(x3, x0);
 }
 
 // Forward 3-D transform of q[16 z + 4 y + x]: x-lines, y-lines, z-lines.
