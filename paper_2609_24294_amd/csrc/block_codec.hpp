@@ -146,27 +146,8 @@ ZFPX_HD void xform_inv(int32_t* q) {
 }
 
 // ---------------------------------------------------------------------------
-// 32x32 bit-matrix transpose in place: afterwards a[r] bit c = old a[c] bit r.
+// Bit transpose
 // ---------------------------------------------------------------------------
-template <int J, uint32_t MASK>
-ZFPX_HD void transpose_stage(uint32_t* a) {
-#pragma unroll
-  for (int r = 0; r < 32; r++) {
-    if ((r & J) == 0) {
-      uint32_t t = ((a[r] >> J) ^ a[r + J]) & MASK;
-      a[r + J] ^= t;
-      a[r] ^= t << J;
-    }
-  }
-}
-
-ZFPX_HD void transpose32(uint32_t* a) {
-  transpose_stage<16, 0x0000ffffu>(a);
-  transpose_stage<8, 0x00ff00ffu>(a);
-  transpose_stage<4, 0x0f0f0f0fu>(a);
-  transpose_stage<2, 0x33333333u>(a);
-  transpose_stage<1, 0x55555555u>(a);
-}
 
 // Two independent 32x32 transposes at once on 64-bit words: a[r] holds row r
 // of the first matrix in its low half and of the second in its high half;
@@ -175,8 +156,7 @@ ZFPX_HD void transpose32(uint32_t* a) {
 // (r & J == 0), the bits whose column has bit J set in row r with the bits
 // whose column has it clear in row r+J.  Stages 16 and 8 move whole bytes
 // (one byte permute per output half); stages 4, 2, 1 are a shift and a
-// bit-field select per output half (the masks keep bits from crossing the
-// 32-bit boundary, so the shifts can act on the 64-bit word).
+// bit-field select per output half.
 
 // Byte permute: result byte i = byte sel_i of (hi:lo), bytes 0-3 from lo.
 ZFPX_HD uint32_t byte_perm(uint32_t hi, uint32_t lo, uint32_t sel) {
@@ -207,16 +187,20 @@ ZFPX_HD void transpose_bytes64(uint64_t* a) {
   }
 }
 
-// Bit select: (a & m) | (b & ~m), one three-input logic instruction.
+// Bit select: (a & m) | (b & ~m), one three-input logic instruction; INV
+// returns its complement, still one instruction.
+template <bool INV = false>
 ZFPX_HD uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA);
+  return __builtin_amdgcn_bitop3_b32(m, a, b, INV ? 0x35 : 0xCA);
 #else
-  return (a & m) | (b & ~m);
+  return INV ? ~((a & m) | (b & ~m)) : (a & m) | (b & ~m);
 #endif
 }
 
-template <int J, uint32_t MASK>
+// INV_HI complements the rows r + J written by the stage (the odd rows when
+// J = 1), at no cost.
+template <int J, uint32_t MASK, bool INV_HI = false>
 ZFPX_HD void transpose_bits64(uint64_t* a) {
   // Each half is shifted on its own: the bits a 64-bit shift would carry
   // across the halves land where the select mask discards them.
@@ -226,19 +210,23 @@ ZFPX_HD void transpose_bits64(uint64_t* a) {
     if ((r & J) == 0) {
       uint32_t xl = (uint32_t)a[r], xh = (uint32_t)(a[r] >> 32);
       uint32_t yl = (uint32_t)a[r + J], yh = (uint32_t)(a[r + J] >> 32);
-      a[r + J] = (uint64_t)bit_select(MASK, xl >> J, yl) |
-                 ((uint64_t)bit_select(MASK, xh >> J, yh) << 32);
+      a[r + J] = (uint64_t)bit_select<INV_HI>(MASK, xl >> J, yl) |
+                 ((uint64_t)bit_select<INV_HI>(MASK, xh >> J, yh) << 32);
       a[r] = (uint64_t)bit_select(HM, yl << J, xl) | ((uint64_t)bit_select(HM, yh << J, xh) << 32);
     }
   }
 }
 
+// INVERT_ODD: afterwards rows 1, 3, ..., 31 are complemented.  XOR with a
+// constant commutes with the transpose, so the encoder's negabinary XOR with
+// 0xaaaaaaaa (bits 1, 3, ..., 31 of every coefficient) becomes exactly this.
+template <bool INVERT_ODD = false>
 ZFPX_HD void transpose32x2(uint64_t* a) {
   transpose_bytes64<16>(a);
   transpose_bytes64<8>(a);
   transpose_bits64<4, 0x0f0f0f0fu>(a);
   transpose_bits64<2, 0x33333333u>(a);
-  transpose_bits64<1, 0x55555555u>(a);
+  transpose_bits64<1, 0x55555555u, INVERT_ODD>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -299,14 +287,16 @@ ZFPX_HD void encode_block(float* v, uint64_t* out, int rate_rt) {
 #pragma unroll
     for (int i = 0; i < 64; i++) q[i] = (int32_t)scale_pow2(v[i], 30 - emax);
     xform_fwd(q);
+    // negabinary (q + mask) ^ mask: the add here, the XOR in the transpose
 #pragma unroll
     for (int s = 0; s < 32; s++) {
-      uint32_t lo = ((uint32_t)q[kSeq.idx[s]] + kNegabinaryMask) ^ kNegabinaryMask;
-      uint32_t hi = ((uint32_t)q[kSeq.idx[32 + s]] + kNegabinaryMask) ^ kNegabinaryMask;
+      uint32_t lo = (uint32_t)q[kSeq.idx[s]] + kNegabinaryMask;
+      uint32_t hi = (uint32_t)q[kSeq.idx[32 + s]] + kNegabinaryMask;
       X[s] = (uint64_t)lo | ((uint64_t)hi << 32);
     }
   }
-  transpose32x2(X);
+  static_assert(kNegabinaryMask == 0xaaaaaaaau, "the transpose complements the odd planes");
+  transpose32x2<true>(X);
   uint32_t pos = 9;
   int n = 0;
 #pragma unroll
