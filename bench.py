@@ -429,6 +429,7 @@ def serving_report(torch, zfpx, W, count):
     words_out = [torch.empty(nx_max // 4 * 16 * 2 * 32, dtype=torch.int64, device=dev)
                  for _ in range(nsets)]
     float_out = [torch.empty_like(pool) for _ in range(nsets)]
+    torch.cuda.synchronize()  # inputs complete before the server's own stream reads them
 
     def build(stream):
         reqs, nbytes = [], []

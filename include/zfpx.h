@@ -238,7 +238,8 @@ int zfpx_graph_destroy(zfpx_graph* graph);
  * zfpx_decode_fixed_rate): op 0 compresses d_in (float32, strides sx,sy,sz)
  * into d_out (coded words, 8-byte aligned); op 1 decompresses d_in (words)
  * into d_out (float32).  Buffers are caller-owned device memory that must stay
- * valid until the request completes.  tag is free for the caller.
+ * valid until the request completes; the device loop runs on its own stream,
+ * so work on other streams that writes them must have completed before submit.  tag is free for the caller.
  *
  * The server realises the paper's point that fixed-rate ZFP needs no
  * coordination between blocks (Section II-C) as a service: requests are

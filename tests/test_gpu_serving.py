@@ -164,3 +164,33 @@ def test_server_large_requests_in_runs(zfpx_lib):
     sv.close()
     torch.cuda.synchronize()
     _check(outs, refs)
+
+
+def test_server_array_beyond_4gib(zfpx_lib):
+    """A request whose float32 array spans more than 4 GiB takes the
+    element-wise coherent path; its results equal the one-launch form."""
+    nx, ny, sz = 64, 8, (1 << 30) + 64  # two levels 4 GiB + 256 B apart
+    base = torch.empty(sz + ny * nx, dtype=torch.float32, device=DEV)
+    rng = np.random.default_rng(44)
+    lev = torch.from_numpy((280 + 15 * rng.standard_normal((2, ny, nx))).astype(np.float32)).to(DEV)
+    base[:ny * nx] = lev[0].reshape(-1)
+    base[sz: sz + ny * nx] = lev[1].reshape(-1)
+    view = torch.as_strided(base, (2, ny, nx), (sz, nx, 1))
+    rate = 16
+    words = zfpx_lib.zfpx_encode_fixed_rate(view, rate)
+    ref = torch.full((2, ny, nx), -7.0, device=DEV)
+    zfpx_lib.zfpx_decode_fixed_rate(words, rate, ref)
+    out_words = torch.zeros_like(words)
+    out_view = torch.as_strided(base, (2, ny, nx), (sz, nx, 1))
+    sv = zfpx_lib.Server(64 << 30, max_slots=4)
+    sv.submit(zfpx_lib.make_request(0, rate, view, out_words))
+    sv.drain(60.0)
+    base.fill_(-7.0)  # the decode writes back into the same strided layout
+    torch.cuda.synchronize()  # the server's loop runs on its own stream
+    sv.submit(zfpx_lib.make_request(1, rate, out_view, words))
+    sv.drain(60.0)
+    sv.close()
+    torch.cuda.synchronize()
+    assert torch.equal(out_words, words)
+    got = torch.stack([base[:ny * nx].reshape(ny, nx), base[sz: sz + ny * nx].reshape(ny, nx)])
+    assert torch.equal(got, ref)
