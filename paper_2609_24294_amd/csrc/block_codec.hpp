@@ -253,10 +253,21 @@ ZFPX_HD void or_bits(uint64_t* s, uint32_t pos, uint64_t code) {
 }
 
 // The 64 stream bits starting at bit position `pos`.
+// Read as 32-bit words (the low word of each 64-bit word first): three words
+// from word pos / 32 hold the window, and two funnel shifts by pos % 32 (which
+// the instruction takes from the low 5 bits of its count) assemble it.
+typedef uint32_t __attribute__((may_alias)) u32_alias;
+ZFPX_HD uint32_t funnel32(uint32_t hi, uint32_t lo, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_alignbit(hi, lo, b);
+#else
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> (b & 31));
+#endif
+}
 ZFPX_HD uint64_t window64(const uint64_t* s, uint32_t pos) {
-  uint32_t w = pos >> 6, b = pos & 63;
-  uint64_t a = s[w], c = s[w + 1];
-  return (a >> b) | ((c << 1) << (63 - b));
+  const u32_alias* d = reinterpret_cast<const u32_alias*>(s) + (pos >> 5);
+  const uint32_t d0 = d[0], d1 = d[1], d2 = d[2];
+  return (uint64_t)funnel32(d1, d0, pos) | ((uint64_t)funnel32(d2, d1, pos) << 32);
 }
 
 // ---------------------------------------------------------------------------
