@@ -18,6 +18,7 @@ One JSON line on stdout.  --gpus N with N > 1 exits: this build runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -182,6 +183,9 @@ def main():
                     "bytes_reduction": 2.0},
         }
         del h
+        if rate == 16:
+            extras["transpose_model"] = transpose_model_report(
+                in_bytes, t_enc, t_dec, e8, d8, tt, tr)
 
     if args.copy_calibration:
         # known traffic for the counter passes: 256 MiB read and 256 MiB
@@ -265,6 +269,19 @@ def main():
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def transpose_model_report(in_bytes, e16, d16, e8, d8, tt, tr):
+    """Row-transposition time at N = 4 ... 121 nodes from the alpha-beta model
+    with the paper's network parameters and the codec rates measured above
+    (GB/s of float32 input)."""
+    from paper_2609_24294_amd import transpose_model as TM
+    gbs = lambda ms: round(in_bytes / (ms * 1e-3) / 1e9, 1)
+    rates = TM.CodecRates(gbs(e16), gbs(d16), gbs(e8), gbs(d8), gbs(tt), gbs(tr))
+    net = TM.Network()
+    return {"network": f"alpha-beta, {net.link_gbps:g} Gb/s links, {net.hops} hops x "
+                       f"{net.hop_us:g} us per message, sqrt(N)-rank row communicators",
+            "codec_gbs_fp32_input": dataclasses.asdict(rates), **TM.summary(rates, net)}
 
 
 def accuracy_report(plan, src, dst, nvals, nblocks, torch, zfpx, W):
