@@ -16,6 +16,7 @@ the paper's error figures (its input data are not available).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -44,6 +45,7 @@ _I32P = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _U32P = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 _U64P = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 _F32P = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_U8P = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
 _I64 = ctypes.c_int64
 _INT = ctypes.c_int
 
@@ -74,6 +76,13 @@ _SIGS = {
     "orc_decode_sample": (None, _CHUNK_ARGS + [_U64P, _INT, _I64P, _I64, _F32P, _I64P, _I32P]),
     "orc_decode_blocks": (None, [_U64P, _I64, _INT, _F32P]),
     "orc_encode_blocks": (None, [_F32P, _I64, _INT, _U64P]),
+    "orc_encode_planes_from": (_I64, [_U32P, _INT, _I64, _U64P, _I64]),
+    "orc_decode_planes_from": (_I64, [_U64P, _I64, _INT, _I64, _U32P]),
+    "orc_block_precision": (_INT, [_INT, _INT, _INT]),
+    "orc_encode_block_var": (_I64, [_F32P, _INT, _INT, _I64, _U64P]),
+    "orc_decode_block_var": (None, [_U64P, _INT, _INT, _I64, _F32P]),
+    "orc_pack_encode_var": (None, _CHUNK_ARGS + [_F32P, _INT, _INT, _INT, _U32P, _U8P, _I64P]),
+    "orc_decode_unpack_var": (None, _CHUNK_ARGS + [_U32P, _U8P, _INT, _INT, _INT, _F32P]),
 }
 
 
@@ -274,6 +283,87 @@ def decode_sample(chunks, words, rate, ids):
     lib().orc_decode_sample(*_chunk_args(chunks), w, int(rate), ids, ids.size,
                             vals.reshape(-1), pos.reshape(-1), ins.reshape(-1))
     return vals, pos, ins.astype(bool)
+
+
+# ---------------------------------------------------------------------------
+# Variable-size modes (fixed precision / fixed accuracy, with a bit cap)
+# ---------------------------------------------------------------------------
+
+# minexp that leaves every float32 block at maxprec planes (precision mode):
+# the smallest double exponent, as in ZFP's description
+MINEXP_NONE = -1074
+
+
+def accuracy_minexp(tolerance: float) -> int:
+    """minexp of accuracy mode: the largest e with 2^e <= tolerance."""
+    if not tolerance > 0:
+        return MINEXP_NONE
+    return math.frexp(float(tolerance))[1] - 1
+
+
+def block_precision(emax, maxprec, minexp):
+    return int(lib().orc_block_precision(int(emax), int(maxprec), int(minexp)))
+
+
+def encode_planes_from(u64, kmin, budget, nwords=None):
+    u = np.ascontiguousarray(u64, dtype=np.uint32)
+    if nwords is None:
+        nwords = (int(budget) + 63) // 64 + 1
+    w = np.zeros(nwords, np.uint64)
+    nbits = lib().orc_encode_planes_from(u, int(kmin), int(budget), w, 0)
+    return w, int(nbits)
+
+
+def decode_planes_from(words, kmin, budget):
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    u = np.zeros(64, np.uint32)
+    nbits = lib().orc_decode_planes_from(w, 0, int(kmin), int(budget), u)
+    return u, int(nbits)
+
+
+def encode_block_var(v64, maxprec, minexp, rate_cap):
+    """-> (words (rate_cap + 1 uint64, zero past the length), length in bits)."""
+    v = np.ascontiguousarray(v64, dtype=np.float32)
+    w = np.zeros(int(rate_cap) + 1, np.uint64)
+    n = lib().orc_encode_block_var(v, int(maxprec), int(minexp), 64 * int(rate_cap), w)
+    return w, int(n)
+
+
+def decode_block_var(words, maxprec, minexp, rate_cap):
+    w = np.zeros(int(rate_cap) + 1, np.uint64)
+    words = np.asarray(words, dtype=np.uint64).reshape(-1)
+    w[:min(words.size, w.size)] = words[:w.size]
+    v = np.zeros(64, np.float32)
+    lib().orc_decode_block_var(w, int(maxprec), int(minexp), 64 * int(rate_cap), v)
+    return v
+
+
+def pack_encode_var(chunks, src, maxprec, minexp, rate_cap):
+    """-> (words uint32[total], nd uint8[nblocks], tile_off int64[ntiles + 1])."""
+    assert 1 <= int(rate_cap) <= 32
+    src = np.ascontiguousarray(src, dtype=np.float32).reshape(-1)
+    nb = int(chunk_blocks(chunks).sum())
+    out = np.zeros(max(1, nb * 2 * int(rate_cap)), np.uint32)
+    nd = np.zeros(max(1, nb), np.uint8)
+    toff = np.zeros((nb + 63) // 64 + 1, np.int64)
+    lib().orc_pack_encode_var(*_chunk_args(chunks), src, int(maxprec), int(minexp),
+                              int(rate_cap), out, nd, toff)
+    return out[:int(toff[-1])].copy(), nd[:nb].copy(), toff
+
+
+def decode_unpack_var(chunks, words, nd, maxprec, minexp, rate_cap, dst):
+    """Decode into `dst` (float32, in place); offsets are rebuilt from nd."""
+    assert dst.dtype == np.float32 and dst.flags.c_contiguous
+    assert 1 <= int(rate_cap) <= 32
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    if w.size == 0:
+        w = np.zeros(1, np.uint32)
+    nd = np.ascontiguousarray(nd, dtype=np.uint8)
+    if nd.size == 0:
+        nd = np.zeros(1, np.uint8)
+    lib().orc_decode_unpack_var(*_chunk_args(chunks), w, nd, int(maxprec), int(minexp),
+                                int(rate_cap), dst.reshape(-1))
+    return dst
 
 
 # ---------------------------------------------------------------------------

@@ -95,11 +95,12 @@ def _plane(u: list[int], k: int) -> list[int]:
     return [(c >> k) & 1 for c in u]
 
 
-def code(u: list[int], budget: int) -> list[int]:
-    """Embedded coding of 64 negabinary words; returns the emitted bits."""
+def code(u: list[int], budget: int, kmin: int = 0) -> list[int]:
+    """Embedded coding of 64 negabinary words, planes 31 down to kmin;
+    returns the emitted bits."""
     out: list[int] = []
     n = 0
-    for k in range(31, -1, -1):
+    for k in range(31, kmin - 1, -1):
         if len(out) >= budget:
             break
         p = _plane(u, k)
@@ -122,7 +123,7 @@ def code(u: list[int], budget: int) -> list[int]:
     return out
 
 
-def uncode(bits: list[int], budget: int) -> list[int]:
+def uncode(bits: list[int], budget: int, kmin: int = 0) -> list[int]:
     u = [0] * 64
     pos = 0
     n = 0
@@ -133,7 +134,7 @@ def uncode(bits: list[int], budget: int) -> list[int]:
         pos += 1
         return b
 
-    for k in range(31, -1, -1):
+    for k in range(31, kmin - 1, -1):
         if pos >= budget:
             break
         p = [0] * 64
@@ -193,3 +194,43 @@ def decode_block(words: list[int], rate: int) -> list[float]:
     q = inverse(c)
     # math.ldexp is exact here; struct packing rounds once, to nearest even
     return [_f32(math.ldexp(float(x), emax - 30)) for x in q]
+
+
+# Variable-size modes: the same coder stopped after p bit planes, where
+# p = min(maxprec, max(0, emax - minexp + 2 (d + 1))) for d = 3 dimensions;
+# p = 0 gives the single bit 0; the length is capped at 64 rate_cap bits.
+
+def planes_for(emax: int, maxprec: int, minexp: int) -> int:
+    return max(0, min(maxprec, emax - minexp + 2 * (3 + 1)))
+
+
+def encode_block_var(v: list[float], maxprec: int, minexp: int, rate_cap: int):
+    """-> (rate_cap + 1 words, length in bits)."""
+    v = [_f32(float(x)) for x in v]
+    nonempty, emax = exponent(v)
+    p = planes_for(emax, maxprec, minexp) if nonempty else 0
+    if p == 0:
+        return [0] * (rate_cap + 1), 1
+    bits = [1] + [((emax + 127) >> i) & 1 for i in range(8)]
+    q = [int(math.ldexp(x, 30 - emax)) for x in v]
+    c = forward(q)
+    perm = sequency()
+    u = [(_s32(c[perm[s]]) + NB) & MASK32 ^ NB for s in range(64)]
+    bits += code(u, 64 * rate_cap - 9, 32 - p)
+    return _bits_to_words(bits, rate_cap + 1), len(bits)
+
+
+def decode_block_var(words: list[int], maxprec: int, minexp: int, rate_cap: int) -> list[float]:
+    bits = _words_to_bits(list(words) + [0])
+    if not bits[0]:
+        return [0.0] * 64
+    emax = sum(bits[1 + i] << i for i in range(8)) - 127
+    p = planes_for(emax, maxprec, minexp)
+    u = uncode(bits[9:], 64 * rate_cap - 9, 32 - p)
+    perm = sequency()
+    c = [0] * 64
+    for s in range(64):
+        c[perm[s]] = _s32((u[s] ^ NB) - NB)
+    q = inverse(c)
+    return [_f32(math.ldexp(float(x), emax - 30)) for x in q]
+

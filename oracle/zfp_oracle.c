@@ -1,8 +1,8 @@
 /*
  * zfp_oracle.c -- TEST INFRASTRUCTURE ONLY.
  *
- * A plain, slow, deliberately unoptimised CPU implementation of ZFP fixed-rate
- * coding of 3-D float32 arrays, used to check the HIP library bit for bit.
+ * A plain, slow, deliberately unoptimised CPU implementation of ZFP coding of
+ * 3-D float32 arrays (fixed rate, and the variable-size modes), used to check the HIP library bit for bit.
  * Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark may load it; the product path never does, and it shares no code,
  * header, table or helper with the HIP library.
@@ -32,6 +32,10 @@
  *      budget   : all 32 bit planes eligible; when the budget runs out in the
  *                 middle of a scan the decoder still sets the bit at the
  *                 current scan position.
+ *  - The variable-size modes (fixed precision, fixed accuracy) that the paper
+ *    names as future work (Sections II-C and III-B) are the same coder
+ *    stopped after a block-dependent number of bit planes; see "Variable-size
+ *    blocks" below for the rule and the stream layout used for them.
  *  - "Parity unpinned": byte compatibility with the ZFP library itself (no
  *    library is available to compare against), and the paper's measured error
  *    values (its input data are not available).
@@ -250,12 +254,12 @@ static uint64_t plane_word(const uint32_t u[NVAL], int k) {
  * test followed by a unary scan to the next set bit; position 63 is implied
  * when the scan reaches it.  Returns the number of bits written.
  */
-int64_t orc_encode_planes(const uint32_t u[NVAL], int64_t budget, uint64_t *words,
-                          int64_t bitpos) {
+int64_t orc_encode_planes_from(const uint32_t u[NVAL], int kmin, int64_t budget,
+                               uint64_t *words, int64_t bitpos) {
   bitwriter w = {words, bitpos};
   int64_t bits = budget;
   int n = 0;
-  for (int k = 31; k >= 0 && bits > 0; k--) {
+  for (int k = 31; k >= kmin && bits > 0; k--) {
     uint64_t x = plane_word(u, k);
     int64_t m = n < bits ? n : bits;
     for (int64_t i = 0; i < m; i++) put_bit(&w, (int)((x >> i) & 1u));
@@ -278,14 +282,20 @@ int64_t orc_encode_planes(const uint32_t u[NVAL], int64_t budget, uint64_t *word
   return w.pos - bitpos;
 }
 
-/* Mirror image of orc_encode_planes; returns the number of bits read. */
-int64_t orc_decode_planes(const uint64_t *words, int64_t bitpos, int64_t budget,
-                          uint32_t u[NVAL]) {
+/* All 32 planes (fixed-rate mode). */
+int64_t orc_encode_planes(const uint32_t u[NVAL], int64_t budget, uint64_t *words,
+                          int64_t bitpos) {
+  return orc_encode_planes_from(u, 0, budget, words, bitpos);
+}
+
+/* Mirror image of orc_encode_planes_from; returns the number of bits read. */
+int64_t orc_decode_planes_from(const uint64_t *words, int64_t bitpos, int kmin, int64_t budget,
+                               uint32_t u[NVAL]) {
   bitreader r = {words, bitpos};
   int64_t bits = budget;
   int n = 0;
   for (int s = 0; s < NVAL; s++) u[s] = 0;
-  for (int k = 31; k >= 0 && bits > 0; k--) {
+  for (int k = 31; k >= kmin && bits > 0; k--) {
     uint64_t x = 0;
     int64_t m = n < bits ? n : bits;
     for (int64_t i = 0; i < m; i++) x |= (uint64_t)get_bit(&r) << i;
@@ -304,6 +314,11 @@ int64_t orc_decode_planes(const uint64_t *words, int64_t bitpos, int64_t budget,
     for (int s = 0; s < NVAL; s++) u[s] |= (uint32_t)((x >> s) & 1u) << k;
   }
   return r.pos - bitpos;
+}
+
+int64_t orc_decode_planes(const uint64_t *words, int64_t bitpos, int64_t budget,
+                          uint32_t u[NVAL]) {
+  return orc_decode_planes_from(words, bitpos, 0, budget, u);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -345,6 +360,82 @@ void orc_decode_block(const uint64_t *words, int rate, float v[NVAL]) {
   int emax = e - 127;
   uint32_t u[NVAL];
   orc_decode_planes(words, r.pos, maxbits - 9, u);
+  int perm[NVAL];
+  orc_sequency_order(perm);
+  int32_t q[NVAL];
+  for (int s = 0; s < NVAL; s++) q[perm[s]] = orc_from_negabinary(u[s]);
+  orc_transform_inverse(q);
+  orc_cast_inverse(q, emax, v);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Variable-size blocks: fixed-precision and fixed-accuracy modes             */
+/* ------------------------------------------------------------------------- */
+/*
+ * The paper (Sections II-C and III-B) names ZFP's two variable-size modes as
+ * the alternative to fixed rate that future work may take up: a fixed number
+ * of bit planes (precision mode) and a fixed absolute error tolerance
+ * (accuracy mode).  In ZFP's description both run the same block coder as
+ * fixed rate but stop after fewer bit planes, with no rate budget:
+ *   - a block with exponent emax codes planes 31 .. 32 - p, where
+ *     p = min(maxprec, max(0, emax - minexp + 2 (d + 1))), d = 3 dimensions
+ *     (the 2 (d + 1) planes cover the growth of the decorrelating transform
+ *     so that the dropped planes stay below 2^minexp);
+ *   - precision mode: maxprec = the precision, minexp unbounded;
+ *   - accuracy mode: maxprec = 32, minexp = floor(log2 tolerance);
+ *   - p = 0, like an all-zero block, is the single bit 0.
+ * Here the block length is also capped at maxbits (ZFP's expert-mode bit
+ * cap); a block that reaches the cap is cut there like a fixed-rate block
+ * and loses the error guarantee.  The block's length is the number of bits
+ * the coder wrote (header included).
+ */
+
+/* Bit planes coded for a block with exponent emax. */
+int orc_block_precision(int emax, int maxprec, int minexp) {
+  int64_t p = (int64_t)emax - (int64_t)minexp + 8;
+  if (p < 0) p = 0;
+  if (p > maxprec) p = maxprec;
+  return (int)p;
+}
+
+/* Encode into zeroed words (at least maxbits / 64 + 1 of them); returns the
+ * length in bits (1 .. maxbits). */
+int64_t orc_encode_block_var(const float v[NVAL], int maxprec, int minexp, int64_t maxbits,
+                             uint64_t *words) {
+  bitwriter w = {words, 0};
+  int emax;
+  int prec = 0;
+  if (orc_block_exponent(v, &emax)) prec = orc_block_precision(emax, maxprec, minexp);
+  if (prec == 0) {
+    put_bit(&w, 0);
+    return 1;
+  }
+  put_bit(&w, 1);
+  for (int i = 0; i < 8; i++) put_bit(&w, ((emax + 127) >> i) & 1);
+  int32_t q[NVAL];
+  orc_cast_forward(v, emax, q);
+  orc_transform_forward(q);
+  int perm[NVAL];
+  orc_sequency_order(perm);
+  uint32_t u[NVAL];
+  for (int s = 0; s < NVAL; s++) u[s] = orc_to_negabinary(q[perm[s]]);
+  return 9 + orc_encode_planes_from(u, 32 - prec, maxbits - 9, words, w.pos);
+}
+
+/* Decode a block made by orc_encode_block_var with the same parameters. */
+void orc_decode_block_var(const uint64_t *words, int maxprec, int minexp, int64_t maxbits,
+                          float v[NVAL]) {
+  bitreader r = {words, 0};
+  if (!get_bit(&r)) {
+    for (int i = 0; i < NVAL; i++) v[i] = 0.0f;
+    return;
+  }
+  int e = 0;
+  for (int i = 0; i < 8; i++) e |= get_bit(&r) << i;
+  int emax = e - 127;
+  int prec = orc_block_precision(emax, maxprec, minexp);
+  uint32_t u[NVAL];
+  orc_decode_planes_from(words, r.pos, 32 - prec, maxbits - 9, u);
   int perm[NVAL];
   orc_sequency_order(perm);
   int32_t q[NVAL];
@@ -585,3 +676,93 @@ void orc_encode_blocks(const float *vals, int64_t nblocks, int rate, uint64_t *o
 #pragma omp parallel for schedule(static)
   for (int64_t j = 0; j < nblocks; j++) orc_encode_block(vals + j * NVAL, rate, out + j * rate);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Variable-size stream of a chunk set                                        */
+/* ------------------------------------------------------------------------- */
+/*
+ * Layout of this library's variable-size mode (a convention of its own, not
+ * ZFP's file format): blocks are numbered across chunks in chunk order as in
+ * fixed rate; block b's bits, LSB first, padded with zeros to whole 32-bit
+ * words, take nd[b] = ceil(len_b / 32) words starting at word
+ * off(b) = nd[0] + ... + nd[b-1] of the output; tile_off[t] = off(64 t) for
+ * t < ceil(nb / 64) and tile_off[ceil(nb / 64)] = the total word count.
+ * Chunk c's message is the words from off(first block of c) to
+ * off(first block of c+1); the per-block counts rebuild every offset.
+ */
+
+/* Dword i of a block coded into 64-bit words (low half first). */
+static uint32_t block_dword(const uint64_t *w, int64_t i) {
+  return (uint32_t)(w[i >> 1] >> (32 * (i & 1)));
+}
+
+void orc_pack_encode_var(int nchunks, const int64_t *chunk_base, const int64_t *level_stride,
+                         const int32_t *levels, const int32_t *row_start,
+                         const int64_t *row_offset, const int32_t *row_len, const float *src,
+                         int maxprec, int minexp, int rate_cap, uint32_t *out, uint8_t *nd,
+                         int64_t *tile_off) {
+  chunk_table t = {nchunks, chunk_base, level_stride, levels, row_start, row_offset, row_len};
+  int64_t *first = (int64_t *)malloc(sizeof(int64_t) * ((size_t)nchunks + 1));
+  first[0] = 0;
+  for (int c = 0; c < nchunks; c++) first[c + 1] = first[c] + chunk_blocks(&t, c);
+  int64_t nb = first[nchunks];
+  int64_t maxbits = 64 * (int64_t)rate_cap, stride = rate_cap + 1;
+  uint64_t *tmp = (uint64_t *)calloc((size_t)(nb > 0 ? nb : 1) * (size_t)stride, 8);
+  int64_t *len = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb > 0 ? nb : 1));
+  for (int c = 0; c < nchunks; c++) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = first[c]; b < first[c + 1]; b++) {
+      float v[NVAL];
+      gather_chunk_block(&t, c, b - first[c], src, v, NULL, NULL);
+      len[b] = orc_encode_block_var(v, maxprec, minexp, maxbits, tmp + b * stride);
+    }
+  }
+  int64_t off = 0;
+  for (int64_t b = 0; b < nb; b++) {
+    if (b % 64 == 0) tile_off[b / 64] = off;
+    int64_t n = (len[b] + 31) / 32;
+    nd[b] = (uint8_t)n;
+    for (int64_t i = 0; i < n; i++) out[off + i] = block_dword(tmp + b * stride, i);
+    off += n;
+  }
+  tile_off[(nb + 63) / 64] = off;
+  free(len);
+  free(tmp);
+  free(first);
+}
+
+/* Decode with offsets rebuilt from nd alone; only chunk points are written. */
+void orc_decode_unpack_var(int nchunks, const int64_t *chunk_base, const int64_t *level_stride,
+                           const int32_t *levels, const int32_t *row_start,
+                           const int64_t *row_offset, const int32_t *row_len,
+                           const uint32_t *in, const uint8_t *nd, int maxprec, int minexp,
+                           int rate_cap, float *dst) {
+  chunk_table t = {nchunks, chunk_base, level_stride, levels, row_start, row_offset, row_len};
+  int64_t *first = (int64_t *)malloc(sizeof(int64_t) * ((size_t)nchunks + 1));
+  first[0] = 0;
+  for (int c = 0; c < nchunks; c++) first[c + 1] = first[c] + chunk_blocks(&t, c);
+  int64_t nb = first[nchunks];
+  int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb + 1));
+  off[0] = 0;
+  for (int64_t b = 0; b < nb; b++) off[b + 1] = off[b] + nd[b];
+  int64_t maxbits = 64 * (int64_t)rate_cap;
+  for (int c = 0; c < nchunks; c++) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = first[c]; b < first[c + 1]; b++) {
+      uint64_t w[64 + 2];
+      memset(w, 0, sizeof w);
+      for (int64_t i = 0; i < nd[b] && i < 2 * (int64_t)rate_cap; i++)
+        w[i >> 1] |= (uint64_t)in[off[b] + i] << (32 * (i & 1));
+      float v[NVAL];
+      int64_t pos[NVAL];
+      int inside[NVAL];
+      gather_chunk_block(&t, c, b - first[c], NULL, NULL, pos, inside);
+      orc_decode_block_var(w, maxprec, minexp, maxbits, v);
+      for (int i = 0; i < NVAL; i++)
+        if (inside[i]) dst[pos[i]] = v[i];
+    }
+  }
+  free(off);
+  free(first);
+}
+
