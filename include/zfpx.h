@@ -182,6 +182,84 @@ int zfpx_decode_unpack_chunks(const zfpx_plan* plan, int32_t first, int32_t coun
                               int64_t dst_elems, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Variable-size modes: fixed precision and fixed accuracy
+ * ---------------------------------------------------------------------- */
+
+/*
+ * ZFP's precision and accuracy modes, which the paper sets aside for future
+ * work because their messages do not have a size known in advance (Sections
+ * II-C and III-B).  They run the fixed-rate block coder but stop after the
+ * bit planes 31 .. 32-p of a block with exponent emax, where
+ *   p = min(maxprec, max(0, emax - minexp + 8))      (8 = 2 (d+1), d = 3);
+ * p = 0 codes the block as the single bit 0.
+ *   precision mode: maxprec in 1..32 and minexp = ZFPX_MINEXP_NONE;
+ *   accuracy mode : maxprec = 32 and minexp = zfpx_accuracy_minexp(tol):
+ *                   every decoded value is within tol of its input, for
+ *                   every block shorter than the cap.
+ * Each block is also capped at 64*rate_cap bits (rate_cap 1..32) and cut
+ * there as a fixed-rate block of that rate would be.
+ *
+ * Stream layout: blocks are numbered as in fixed rate (chunk order).  Block
+ * b's bits, least significant first and zero padded, take nd[b] =
+ * ceil(bits/32) 32-bit words (1 .. 2*rate_cap) starting at word
+ * nd[0] + ... + nd[b-1].  tile_off[t] is the word offset of block 64*t for
+ * t < ntiles = ceil(nblocks/64); tile_off[ntiles] is the total word count.
+ * Chunk c's message is the words between the offsets of its first block and
+ * of the next chunk's first block (zfpx_plan_var_chunk_offsets); its nd
+ * entries rebuild every offset inside it.
+ */
+#define ZFPX_MINEXP_NONE (-1074)
+
+/* minexp of accuracy mode: the largest e with 2^e <= tolerance
+ * (ZFPX_MINEXP_NONE for a tolerance that is not positive). */
+int zfpx_accuracy_minexp(double tolerance);
+
+/* Sizes for a plan: the largest stream in 32-bit words (every block at the
+ * cap), the tile count (tile_off has ntiles + 1 entries) and the bytes of the
+ * encoder's scratch table.  Any pointer may be NULL. */
+int zfpx_plan_var_sizes(const zfpx_plan* plan, int rate_cap, int64_t* max_words,
+                        int64_t* ntiles, size_t* work_bytes);
+
+/*
+ * Encode every chunk of the plan in a variable-size mode (one launch).
+ *   d_words    : device, 4-byte aligned; words at or past words_bytes/4 are
+ *                not written (the stream is then incomplete: compare
+ *                tile_off[ntiles] with the capacity after synchronising; a
+ *                capacity of max_words never runs out).
+ *   d_nd       : device, nblocks bytes.
+ *   d_tile_off : device, 8-byte aligned, ntiles + 1 entries.
+ *   d_work     : device scratch of at least work_bytes (ENOSPC otherwise),
+ *                8-byte aligned, contents ignored: the call clears it with a
+ *                kernel first.  Calls that overlap in time need separate
+ *                scratch.  After the call, word 1 of the scratch is 1 if a
+ *                tile waited for its predecessors beyond the kernel's bound
+ *                (then the stream is invalid), else 0.
+ * Errors: EINVAL for bad parameters (maxprec 1..32, minexp
+ * ZFPX_MINEXP_NONE..1024, rate_cap 1..32), null or misaligned pointers or a
+ * too small source.
+ */
+int zfpx_plan_encode_var(const zfpx_plan* plan, const float* d_src, int64_t src_elems,
+                         int maxprec, int minexp, int rate_cap, uint32_t* d_words,
+                         size_t words_bytes, uint8_t* d_nd, int64_t* d_tile_off, void* d_work,
+                         size_t work_bytes, void* stream);
+
+/*
+ * Decode a stream made by zfpx_plan_encode_var with the same plan and
+ * parameters into the plan's points of d_dst.  Any content of the words,
+ * counts and offsets decodes without a fault: counts are clamped to
+ * 2*rate_cap and words at or past words_bytes/4 read as zero.
+ */
+int zfpx_plan_decode_var(const zfpx_plan* plan, const uint32_t* d_words, size_t words_bytes,
+                         const uint8_t* d_nd, const int64_t* d_tile_off, int maxprec, int minexp,
+                         int rate_cap, float* d_dst, int64_t dst_elems, void* stream);
+
+/* Word offset of each chunk's first block into d_chunk_off[0..nchunks-1] and
+ * the total into d_chunk_off[nchunks] (device, 8-byte aligned): the counts
+ * and displacements of an all-to-all(v) of the chunks. */
+int zfpx_plan_var_chunk_offsets(const zfpx_plan* plan, const uint8_t* d_nd,
+                                const int64_t* d_tile_off, int64_t* d_chunk_off, void* stream);
+
+/* -------------------------------------------------------------------------
  * Launch configuration and autotuning
  * ---------------------------------------------------------------------- */
 

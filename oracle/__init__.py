@@ -83,6 +83,8 @@ _SIGS = {
     "orc_decode_block_var": (None, [_U64P, _INT, _INT, _I64, _F32P]),
     "orc_pack_encode_var": (None, _CHUNK_ARGS + [_F32P, _INT, _INT, _INT, _U32P, _U8P, _I64P]),
     "orc_decode_unpack_var": (None, _CHUNK_ARGS + [_U32P, _U8P, _INT, _INT, _INT, _F32P]),
+    "orc_pack_encode_var_sample": (None, _CHUNK_ARGS + [_F32P, _INT, _INT, _INT, _I64P, _I64,
+                                                        _U64P, _I64P, _I64P, _I32P]),
 }
 
 
@@ -349,6 +351,21 @@ def pack_encode_var(chunks, src, maxprec, minexp, rate_cap):
     lib().orc_pack_encode_var(*_chunk_args(chunks), src, int(maxprec), int(minexp),
                               int(rate_cap), out, nd, toff)
     return out[:int(toff[-1])].copy(), nd[:nb].copy(), toff
+
+
+def pack_encode_var_sample(chunks, src, maxprec, minexp, rate_cap, ids):
+    """Listed blocks only: (words (n, rate_cap + 1), bits (n,), offsets (n, 64),
+    inside (n, 64))."""
+    src = np.ascontiguousarray(src, dtype=np.float32).reshape(-1)
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    out = np.zeros((ids.size, int(rate_cap) + 1), np.uint64)
+    ln = np.zeros(ids.size, np.int64)
+    pos = np.zeros((ids.size, 64), np.int64)
+    ins = np.zeros((ids.size, 64), np.int32)
+    lib().orc_pack_encode_var_sample(*_chunk_args(chunks), src, int(maxprec), int(minexp),
+                                     int(rate_cap), ids, ids.size, out.reshape(-1), ln,
+                                     pos.reshape(-1), ins.reshape(-1))
+    return out, ln, pos, ins.astype(bool)
 
 
 def decode_unpack_var(chunks, words, nd, maxprec, minexp, rate_cap, dst):

@@ -766,3 +766,32 @@ void orc_decode_unpack_var(int nchunks, const int64_t *chunk_base, const int64_t
   free(first);
 }
 
+
+/* Encode only the listed global block ids in a variable-size mode: block
+ * j's words (zero past its length) at out[j * (rate_cap + 1)], its length in
+ * bits at len[j], and its element offsets / in-range flags at pos[j * 64] and
+ * inside[j * 64].  Used to check very large buffers on a sample of blocks. */
+void orc_pack_encode_var_sample(int nchunks, const int64_t *chunk_base,
+                                const int64_t *level_stride, const int32_t *levels,
+                                const int32_t *row_start, const int64_t *row_offset,
+                                const int32_t *row_len, const float *src, int maxprec,
+                                int minexp, int rate_cap, const int64_t *ids, int64_t nids,
+                                uint64_t *out, int64_t *len, int64_t *pos, int32_t *inside) {
+  chunk_table t = {nchunks, chunk_base, level_stride, levels, row_start, row_offset, row_len};
+  int64_t *first = (int64_t *)malloc(sizeof(int64_t) * ((size_t)nchunks + 1));
+  first[0] = 0;
+  for (int c = 0; c < nchunks; c++) first[c + 1] = first[c] + chunk_blocks(&t, c);
+  int64_t stride = rate_cap + 1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t j = 0; j < nids; j++) {
+    int c = 0;
+    while (c + 1 < nchunks && first[c + 1] <= ids[j]) c++;
+    float v[NVAL];
+    int ins[NVAL];
+    gather_chunk_block(&t, c, ids[j] - first[c], src, v, pos + j * NVAL, ins);
+    memset(out + j * stride, 0, (size_t)stride * sizeof(uint64_t));
+    len[j] = orc_encode_block_var(v, maxprec, minexp, 64 * (int64_t)rate_cap, out + j * stride);
+    for (int i = 0; i < NVAL; i++) inside[j * NVAL + i] = ins[i];
+  }
+  free(first);
+}

@@ -2,6 +2,7 @@
 // configuration, autotuning and HIP-graph capture.  Hot-path entry points only
 // check arguments on the host and enqueue kernels.
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
@@ -51,6 +52,7 @@ struct zfpx_plan {
   SegDesc* d_segs = nullptr;
   int32_t* d_seg_block0 = nullptr;
   int32_t* d_tile_seg = nullptr;
+  int64_t* d_chunk_first = nullptr;  // [nchunks + 1], for the variable-size chunk offsets
   PlanDev dev{};
   std::map<std::pair<int, int>, LaunchCfg> cfg;  // (op, rate) -> config; rate 0 = any
 
@@ -152,6 +154,7 @@ int zfpx_plan_destroy(zfpx_plan* p) {
   if (p->d_segs) (void)hipFree(p->d_segs);
   if (p->d_seg_block0) (void)hipFree(p->d_seg_block0);
   if (p->d_tile_seg) (void)hipFree(p->d_tile_seg);
+  if (p->d_chunk_first) (void)hipFree(p->d_chunk_first);
   delete p;
   return ZFPX_OK;
 }
@@ -268,6 +271,17 @@ int zfpx_plan_create(int32_t nchunks, const int64_t* chunk_base, const int64_t* 
       return ZFPX_EHIP;
     }
   }
+  if (total > 0) {
+    if (hipMalloc(&p->d_chunk_first, (nchunks + 1) * sizeof(int64_t)) != hipSuccess) {
+      zfpx_plan_destroy(p);
+      return ZFPX_ENOMEM;
+    }
+    if (hipMemcpy(p->d_chunk_first, p->chunk_first.data(), (nchunks + 1) * sizeof(int64_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      zfpx_plan_destroy(p);
+      return ZFPX_EHIP;
+    }
+  }
   p->dev = PlanDev{p->d_segs, p->d_seg_block0, p->d_tile_seg};
   (void)device_cu_count();  // device facts are queried here, outside any capture
   *out = p;
@@ -356,6 +370,77 @@ int zfpx_decode_unpack_chunks(const zfpx_plan* p, int32_t first, int32_t count,
                               const void* d_recv, size_t recv_bytes, int rate, float* d_dst,
                               int64_t dst_elems, void* stream) {
   return do_decode_unpack(p, first, count, d_recv, recv_bytes, rate, d_dst, dst_elems, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Variable-size modes
+// ---------------------------------------------------------------------------
+
+static bool var_params_ok(int maxprec, int minexp, int rate_cap) {
+  return maxprec >= 1 && maxprec <= 32 && minexp >= ZFPX_MINEXP_NONE && minexp <= 1024 &&
+         rate_ok(rate_cap);
+}
+
+int zfpx_accuracy_minexp(double tolerance) {
+  if (!(tolerance > 0) || tolerance != tolerance) return ZFPX_MINEXP_NONE;
+  int e = 0;
+  (void)frexp(tolerance, &e);  // tolerance = f 2^e, f in [1/2, 1)
+  return e - 1;
+}
+
+int zfpx_plan_var_sizes(const zfpx_plan* p, int rate_cap, int64_t* max_words, int64_t* ntiles,
+                        size_t* work_bytes) {
+  if (!p || !rate_ok(rate_cap)) return ZFPX_EINVAL;
+  if (max_words) *max_words = p->nblocks * 2 * rate_cap;
+  if (ntiles) *ntiles = (p->nblocks + 63) / 64;
+  if (work_bytes) *work_bytes = var_table_words(p->nblocks) * sizeof(uint64_t);
+  return ZFPX_OK;
+}
+
+int zfpx_plan_encode_var(const zfpx_plan* p, const float* d_src, int64_t src_elems, int maxprec,
+                         int minexp, int rate_cap, uint32_t* d_words, size_t words_bytes,
+                         uint8_t* d_nd, int64_t* d_tile_off, void* d_work, size_t work_bytes,
+                         void* stream) {
+  if (!p || !var_params_ok(maxprec, minexp, rate_cap)) return ZFPX_EINVAL;
+  if (p->nblocks == 0) return ZFPX_OK;
+  if (!d_src || !d_words || !d_nd || !d_tile_off || !d_work || !aligned(d_words, 4) ||
+      !aligned(d_tile_off, 8) || !aligned(d_work, 8) || src_elems < p->min_elems)
+    return ZFPX_EINVAL;
+  if (work_bytes < var_table_words(p->nblocks) * sizeof(uint64_t)) return ZFPX_ENOSPC;
+  bool vec4 = p->vec4 && aligned(d_src, 16);
+  hipError_t e = launch_plan_encode_var(p->dev, vec4, d_src, d_words, words_bytes / 4, d_nd,
+                                        d_tile_off, (uint64_t*)d_work, rate_cap,
+                                        (int32_t)p->nblocks, maxprec, minexp, (hipStream_t)stream);
+  return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
+}
+
+int zfpx_plan_decode_var(const zfpx_plan* p, const uint32_t* d_words, size_t words_bytes,
+                         const uint8_t* d_nd, const int64_t* d_tile_off, int maxprec, int minexp,
+                         int rate_cap, float* d_dst, int64_t dst_elems, void* stream) {
+  if (!p || !var_params_ok(maxprec, minexp, rate_cap)) return ZFPX_EINVAL;
+  if (p->nblocks == 0) return ZFPX_OK;
+  if (!d_words || !d_nd || !d_tile_off || !d_dst || !aligned(d_words, 4) ||
+      !aligned(d_tile_off, 8) || dst_elems < p->min_elems)
+    return ZFPX_EINVAL;
+  bool vec4 = p->vec4 && aligned(d_dst, 16);
+  hipError_t e = launch_plan_decode_var(p->dev, vec4, d_words, words_bytes / 4, d_nd, d_tile_off,
+                                        d_dst, rate_cap, (int32_t)p->nblocks, maxprec, minexp,
+                                        (hipStream_t)stream);
+  return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
+}
+
+int zfpx_plan_var_chunk_offsets(const zfpx_plan* p, const uint8_t* d_nd,
+                                const int64_t* d_tile_off, int64_t* d_chunk_off, void* stream) {
+  if (!p || !d_chunk_off || !aligned(d_chunk_off, 8)) return ZFPX_EINVAL;
+  if (p->nblocks > 0 && (!d_nd || !d_tile_off || !aligned(d_tile_off, 8))) return ZFPX_EINVAL;
+  if (p->nblocks == 0) {
+    hipError_t e = launch_fill_u64((uint64_t*)d_chunk_off, p->nchunks + 1, 0,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
+  }
+  hipError_t e = launch_var_chunk_offsets(p->d_chunk_first, p->nchunks, d_nd, d_tile_off,
+                                          d_chunk_off, (hipStream_t)stream);
+  return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
 }
 
 // ---------------------------------------------------------------------------

@@ -18,6 +18,13 @@
 //   further coefficients significant; the last position is implied when a
 //   scan reaches it; when the budget runs out the rest is zero.
 //
+// Variable-size modes (fixed precision, fixed accuracy) run the same coder
+// but stop after the bit planes 31 .. 32 - p, p = min(maxprec, max(0,
+// emax - minexp + 2 (d + 1))) with d = 3 (ZFP's rule for its precision and
+// accuracy modes, which the paper names as the variable-size alternative);
+// p = 0 makes the block the single bit 0.  The defaults of maxprec and minexp
+// give p = 32 for every float block, which is fixed rate.
+//
 // The functions are __host__ __device__ so that the same logic can be built
 // for the CPU when debugging; the library itself only runs them on the GPU.
 #pragma once
@@ -35,6 +42,13 @@
 namespace zfpx {
 
 constexpr uint32_t kNegabinaryMask = 0xaaaaaaaau;
+constexpr int kMinExpNone = -1074;  // no exponent floor: every block keeps maxprec planes
+
+// Bit planes coded for a block with exponent emax.
+ZFPX_HD int block_precision(int emax, int maxprec, int minexp) {
+  const int p = emax - minexp + 8;
+  return p < 0 ? 0 : (p > maxprec ? maxprec : p);
+}
 
 // ---------------------------------------------------------------------------
 // Sequency order, computed at compile time by sorting the 64 block-local
@@ -277,9 +291,11 @@ ZFPX_HD uint64_t window64(const uint64_t* s, uint32_t pos) {
 // Encode one block of 64 floats (v[16 z + 4 y + x]) into the slice `out`,
 // which must hold rate + kSlackWords zero words.  Bits are ORed in place;
 // the slack words may receive bits past the budget and are not part of the
-// stream.  v is clobbered.
+// stream.  v is clobbered.  Returns the block's length in bits (at most
+// 64 * rate; 1 for a block coded as the single bit 0).
 template <int RATE>
-ZFPX_HD void encode_block(float* v, uint64_t* out, int rate_rt) {
+ZFPX_HD uint32_t encode_block(float* v, uint64_t* out, int rate_rt, int maxprec = 32,
+                              int minexp = kMinExpNone) {
   const int rate = RATE > 0 ? RATE : rate_rt;
   const uint32_t maxbits = 64u * (uint32_t)rate;
   // block exponent from the largest magnitude (its biased exponent field)
@@ -287,8 +303,10 @@ ZFPX_HD void encode_block(float* v, uint64_t* out, int rate_rt) {
 #pragma unroll
   for (int i = 0; i < 64; i++) amax = __builtin_fmaxf(amax, __builtin_fabsf(v[i]));
   uint32_t mx = f32_bits(amax);
-  if (mx == 0) return;  // empty block: the single bit 0, all zero
+  if (mx == 0) return 1;  // empty block: the single bit 0, all zero
   int emax = (int)(mx >> 23) - 126;  // subnormal maximum (field 0) gives -126
+  const int kmin = 32 - block_precision(emax, maxprec, minexp);
+  if (kmin == 32) return 1;  // no plane to code: the single bit 0
   or_bits(out, 0, 1u | ((uint64_t)((emax + 127) & 0xff) << 1));
   // X[s] = coefficients s and 32+s (negabinary); after the transpose X[k] is
   // bit plane k: bit s of X[k] = bit k of coefficient s
@@ -312,7 +330,7 @@ ZFPX_HD void encode_block(float* v, uint64_t* out, int rate_rt) {
   int n = 0;
 #pragma unroll
   for (int k = 31; k >= 0; k--) {
-    if (pos < maxbits) {
+    if (pos < maxbits && k >= kmin) {
       uint64_t x = X[k];
       uint64_t y = n < 64 ? (x >> n) : 0;  // bits not yet significant
       or_bits(out, pos, x & low_mask(n));  // the first n bits verbatim
@@ -354,6 +372,7 @@ ZFPX_HD void encode_block(float* v, uint64_t* out, int rate_rt) {
       pos += n < 64 ? 1 : 0;  // group test 0 (a zero bit)
     }
   }
+  return pos < maxbits ? pos : maxbits;
 }
 
 // ---------------------------------------------------------------------------
@@ -363,22 +382,24 @@ ZFPX_HD void encode_block(float* v, uint64_t* out, int rate_rt) {
 // Decode the slice `in` (rate words followed by kSlackWords zero words) into
 // 64 floats (block-local order).
 template <int RATE>
-ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt) {
+ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxprec = 32,
+                          int minexp = kMinExpNone) {
   const int rate = RATE > 0 ? RATE : rate_rt;
   const uint32_t maxbits = 64u * (uint32_t)rate;
   uint64_t head = in[0];
   uint32_t pos = maxbits;  // an empty block decodes to zeros
-  int emax = 0;
+  int emax = 0, kmin = 0;
   if (head & 1) {
     emax = (int)((head >> 1) & 0xff) - 127;
     pos = 9;
+    kmin = 32 - block_precision(emax, maxprec, minexp);
   }
   uint64_t X[32];  // bit planes, then (after the transpose) coefficients s, 32+s
   int n = 0;
 #pragma unroll
   for (int k = 31; k >= 0; k--) {
     uint64_t x = 0;
-    if (pos < maxbits) {
+    if (pos < maxbits && k >= kmin) {
       int m = (int)(maxbits - pos) < n ? (int)(maxbits - pos) : n;
       x = window64(in, pos) & low_mask(m);  // the first n bits verbatim
       pos += m;

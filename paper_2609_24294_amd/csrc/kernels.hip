@@ -432,6 +432,197 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 
 
 // ---------------------------------------------------------------------------
+// Variable-size modes (fixed precision, fixed accuracy)
+// ---------------------------------------------------------------------------
+// Block b takes nd[b] = ceil(bits / 32) 32-bit words at word offset
+// nd[0] + ... + nd[b-1].  A wavefront codes a 64-block tile as in fixed rate,
+// then needs the tile's offset: the sum of the word counts of all earlier
+// tiles.  Tiles publish their own count and then, once known, their end
+// offset in a table of 64-bit states (single-pass scan with decoupled
+// look-back): a tile sums the counts of its predecessors back to the nearest
+// one whose end offset is known.  Wavefronts take tile numbers from a counter
+// in the order they start, so every earlier tile belongs to a wavefront that
+// is running and publishes its count without waiting for anything: the wait
+// always ends.  It is also bounded: after kVarSpinLimit polls the wavefront
+// records a timeout in the table's status word and goes on.
+
+// Scratch table (zeroed before each encode): [0] tile counter, [1] status,
+// [2 + t] state of tile t: kind in bits 62-63, words in bits 0-61.
+constexpr uint64_t kVarAgg = 1ull << 62;    // the tile's own word count
+constexpr uint64_t kVarIncl = 2ull << 62;   // words of tiles 0..t (its end offset)
+constexpr uint64_t kVarValue = (1ull << 62) - 1;
+constexpr uint32_t kVarSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void var_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t var_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Publish tile t's word count, find the words of all earlier tiles, publish
+// the tile's end offset; returns the tile's first word.
+__device__ __forceinline__ uint64_t var_lookback(uint64_t* table, uint32_t t, uint64_t count,
+                                                 int lane) {
+  uint64_t* state = table + 2;
+  if (t == 0) {
+    if (lane == 0) var_store(state, kVarIncl | count);
+    return 0;
+  }
+  if (lane == 0) var_store(state + t, kVarAgg | count);
+  uint64_t before = 0;
+  int64_t j = (int64_t)t - 1;  // newest tile not yet summed
+  uint32_t polls = 0;
+  for (;;) {
+    const int64_t k = j - lane;
+    const uint64_t st = k >= 0 ? var_load(state + k) : kVarIncl;
+    const uint64_t incl = __ballot((st >> 62) == 2);
+    const uint64_t none = __ballot((st >> 62) == 0);
+    const int stop = incl ? __builtin_ctzll(incl) : 63;  // lanes 0..stop are needed
+    const uint64_t need = stop == 63 ? ~0ull : ((2ull << stop) - 1);
+    if (none & need) {
+      if (++polls >= kVarSpinLimit) {
+        if (lane == 0) var_store(table + 1, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    before += wave_sum64(lane <= stop ? (st & kVarValue) : 0);
+    if (incl) break;
+    j -= 64;
+  }
+  if (lane == 0) var_store(state + t, kVarIncl | (before + count));
+  return before;
+}
+
+template <int CAP, bool VEC4, class Geo>
+__global__ __launch_bounds__(256) void k_encode_var(Geo geo, const float* __restrict__ src,
+                                                    uint32_t* __restrict__ out, uint64_t out_words,
+                                                    uint8_t* __restrict__ nd_out,
+                                                    int64_t* __restrict__ tile_off,
+                                                    uint64_t* table, int cap_rt, int32_t nblocks,
+                                                    int maxprec, int minexp) {
+  extern __shared__ uint64_t lds[];
+  const int cap = CAP > 0 ? CAP : cap_rt;
+  const int stride = lds_stride(cap);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint64_t* slice = lds + (size_t)(wave * 64 + lane) * stride;
+  const uint32_t ntiles = (uint32_t)(nblocks + 63) >> 6;
+  uint32_t t = 0;
+  if (lane == 0)
+    t = (uint32_t)__hip_atomic_fetch_add(table, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  t = __builtin_amdgcn_readfirstlane(t);
+  if (t >= ntiles) return;
+  const int32_t b0 = (int32_t)(t << 6);
+  const int nact = nblocks - b0 < 64 ? nblocks - b0 : 64;
+  for (int i = 0; i < stride; i++) slice[i] = 0;
+  uint32_t bits = 0;
+  if (lane < nact) {
+    BlockView v;
+    geo.locate_tile(b0, lane, nact, v);
+    float val[64];
+    gather<VEC4>(src, v, val);
+    bits = encode_block<CAP>(val, slice, cap, maxprec, minexp);
+  }
+  const uint32_t nd = (bits + 31) >> 5;
+  if (lane < nact) nd_out[b0 + lane] = (uint8_t)nd;
+  const uint32_t incl = wave_incl_scan(nd, lane);
+  const uint32_t count = __builtin_amdgcn_readlane(incl, 63);
+  const uint64_t first = var_lookback(table, t, count, lane);
+  if (lane == 0) {
+    tile_off[t] = (int64_t)first;
+    if (t == ntiles - 1) tile_off[ntiles] = (int64_t)(first + count);
+  }
+  wave_sync_lds();
+  const uint32_t* s32 = reinterpret_cast<const uint32_t*>(slice);
+  const uint64_t o = first + (incl - nd);
+  for (uint32_t i = 0; i < nd; i++)
+    if (o + i < out_words) out[o + i] = s32[i];
+}
+
+// Any content of the stream, counts and offsets decodes without a fault:
+// counts are clamped to the cap and words outside the stream read as zero.
+template <int CAP, bool VEC4, class Geo>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_decode_var(
+    Geo geo, const uint32_t* __restrict__ in, uint64_t in_words, const uint8_t* __restrict__ nd_in,
+    const int64_t* __restrict__ tile_off, float* __restrict__ dst, int cap_rt, int32_t nblocks,
+    int maxprec, int minexp) {
+  extern __shared__ uint64_t lds[];
+  const int cap = CAP > 0 ? CAP : cap_rt;
+  const int stride = lds_stride(cap);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int waves = blockDim.x >> 6;
+  uint64_t* slice = lds + (size_t)(wave * 64 + lane) * stride;
+  const int32_t ntiles = (nblocks + 63) >> 6;
+  const int32_t t = blockIdx.x * waves + wave;
+  if (t >= ntiles) return;
+  const int32_t b0 = t << 6;
+  const int nact = nblocks - b0 < 64 ? nblocks - b0 : 64;
+  uint32_t nd = lane < nact ? nd_in[b0 + lane] : 0;
+  nd = nd < 2u * cap ? nd : 2u * cap;
+  const uint32_t incl = wave_incl_scan(nd, lane);
+  const uint64_t o = (uint64_t)uniform_load(tile_off, t) + (incl - nd);
+  for (int i = 0; i < stride; i++) slice[i] = 0;
+  uint32_t* s32 = reinterpret_cast<uint32_t*>(slice);
+  for (uint32_t i0 = 0; i0 < nd; i0 += 8) {
+    uint32_t r[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const uint64_t w = o + i0 + j;
+      r[j] = (i0 + j < nd && w < in_words && w >= o) ? in[w] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+      if (i0 + j < nd) s32[i0 + j] = r[j];
+  }
+  wave_sync_lds();
+  if (lane < nact) {
+    float val[64];
+    decode_block<CAP>(slice, val, cap, maxprec, minexp);
+    BlockView v;
+    geo.locate_tile(b0, lane, nact, v);
+    scatter<VEC4>(dst, v, val);
+  }
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Word offset of each chunk's first block (and the total at index nchunks).
+__global__ void k_var_chunk_offsets(const int64_t* __restrict__ chunk_first, int32_t nchunks,
+                                    const uint8_t* __restrict__ nd,
+                                    const int64_t* __restrict__ tile_off,
+                                    int64_t* __restrict__ chunk_off) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > nchunks) return;
+  const int64_t b = chunk_first[c];
+  int64_t o = tile_off[b >> 6];
+  for (int64_t i = b & ~(int64_t)63; i < b; i++) o += nd[i];
+  chunk_off[c] = o;
+}
+
+// ---------------------------------------------------------------------------
 // Serving loop
 // ---------------------------------------------------------------------------
 // Wavefront 0 of workgroup 0 is the dispatcher: it alone polls the host's
@@ -900,6 +1091,81 @@ hipError_t launch_f16_restore(const uint16_t* in, size_t n, float* out, hipStrea
   if (done < n)
     hipLaunchKernelGGL(k_f16_restore_s, dim3(elementwise_grid(n - done)), dim3(256), 0, s,
                        in + done, n - done, out + done);
+  return hipGetLastError();
+}
+
+#define ZFPX_CAP_SWITCH(KERNEL, GEO, VEC4, ...)                                     \
+  switch (cap) {                                                                   \
+    case 8:                                                                        \
+      hipLaunchKernelGGL((KERNEL<8, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);  \
+      break;                                                                       \
+    case 16:                                                                       \
+      hipLaunchKernelGGL((KERNEL<16, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__); \
+      break;                                                                       \
+    case 32:                                                                       \
+      hipLaunchKernelGGL((KERNEL<32, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__); \
+      break;                                                                       \
+    default:                                                                       \
+      hipLaunchKernelGGL((KERNEL<0, VEC4, GEO>), grid, block, shm, s, __VA_ARGS__);  \
+      break;                                                                       \
+  }
+
+size_t var_table_words(int64_t nblocks) { return (size_t)((nblocks + 63) >> 6) + 2; }
+
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)(g < 1024 ? g : 1024)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_encode_var(const PlanDev& p, bool vec4, const float* src, uint32_t* out,
+                                  uint64_t out_words, uint8_t* nd, int64_t* tile_off,
+                                  uint64_t* table, int cap, int32_t nblocks, int maxprec,
+                                  int minexp, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipError_t e = launch_fill_u64(table, (int64_t)var_table_words(nblocks), 0, s);
+  if (e != hipSuccess) return e;
+  constexpr int wg = 128;
+  const int ntiles = (nblocks + 63) >> 6;
+  dim3 grid((ntiles + wg / 64 - 1) / (wg / 64)), block(wg);
+  size_t shm = lds_bytes(wg, cap);
+  PlanGeo geo{p};
+  if (vec4) {
+    ZFPX_CAP_SWITCH(k_encode_var, PlanGeo, true, geo, src, out, out_words, nd, tile_off, table,
+                    cap, nblocks, maxprec, minexp);
+  } else {
+    ZFPX_CAP_SWITCH(k_encode_var, PlanGeo, false, geo, src, out, out_words, nd, tile_off, table,
+                    cap, nblocks, maxprec, minexp);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_decode_var(const PlanDev& p, bool vec4, const uint32_t* in,
+                                  uint64_t in_words, const uint8_t* nd, const int64_t* tile_off,
+                                  float* dst, int cap, int32_t nblocks, int maxprec, int minexp,
+                                  hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  constexpr int wg = 128;
+  const int ntiles = (nblocks + 63) >> 6;
+  dim3 grid((ntiles + wg / 64 - 1) / (wg / 64)), block(wg);
+  size_t shm = lds_bytes(wg, cap);
+  PlanGeo geo{p};
+  if (vec4) {
+    ZFPX_CAP_SWITCH(k_decode_var, PlanGeo, true, geo, in, in_words, nd, tile_off, dst, cap,
+                    nblocks, maxprec, minexp);
+  } else {
+    ZFPX_CAP_SWITCH(k_decode_var, PlanGeo, false, geo, in, in_words, nd, tile_off, dst, cap,
+                    nblocks, maxprec, minexp);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_var_chunk_offsets(const int64_t* chunk_first, int32_t nchunks,
+                                    const uint8_t* nd, const int64_t* tile_off,
+                                    int64_t* chunk_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_var_chunk_offsets, dim3((nchunks + 1 + 255) / 256), dim3(256), 0, s,
+                     chunk_first, nchunks, nd, tile_off, chunk_off);
   return hipGetLastError();
 }
 

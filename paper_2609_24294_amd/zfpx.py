@@ -65,6 +65,12 @@ _SIGS = {
     "zfpx_server_destroy": (_INT, [_P]),
     "zfpx_server_replay": (_INT, [_P, _P, _P, _I64, _c.c_double, _P]),
     "zfpx_plain_replay": (_INT, [_P, _P, _I64, _c.c_double, _P, _P]),
+    "zfpx_accuracy_minexp": (_INT, [_c.c_double]),
+    "zfpx_plan_var_sizes": (_INT, [_P, _INT, _PI64, _PI64, _c.POINTER(_SZ)]),
+    "zfpx_plan_encode_var": (_INT, [_P, _P, _I64, _INT, _INT, _INT, _P, _SZ, _P, _P, _P, _SZ,
+                                    _P]),
+    "zfpx_plan_decode_var": (_INT, [_P, _P, _SZ, _P, _P, _INT, _INT, _INT, _P, _I64, _P]),
+    "zfpx_plan_var_chunk_offsets": (_INT, [_P, _P, _P, _P, _P]),
     "f16_truncate": (_INT, [_P, _SZ, _P, _P]),
     "f16_restore": (_INT, [_P, _SZ, _P, _P]),
 }
@@ -257,6 +263,70 @@ def zfpx_decode_unpack_chunks(plan: Plan, first: int, count: int, recv: torch.Te
                                           rate, _dev(dst, torch.float32), dst.numel(),
                                           _stream(stream)), "zfpx_decode_unpack_chunks")
     return dst
+
+
+# ---------------------------------------------------------------------------
+# Variable-size modes (fixed precision / fixed accuracy)
+# ---------------------------------------------------------------------------
+
+MINEXP_NONE = -1074  # ZFPX_MINEXP_NONE: precision mode (no exponent floor)
+
+
+def zfpx_accuracy_minexp(tolerance: float) -> int:
+    return _lib.zfpx_accuracy_minexp(float(tolerance))
+
+
+def zfpx_plan_var_sizes(plan: Plan, rate_cap: int):
+    """(largest stream in 32-bit words, tiles, scratch bytes)."""
+    mw, nt, wb = _I64(), _I64(), _SZ()
+    _check(_lib.zfpx_plan_var_sizes(plan.handle, rate_cap, _c.byref(mw), _c.byref(nt),
+                                    _c.byref(wb)), "zfpx_plan_var_sizes")
+    return mw.value, nt.value, wb.value
+
+
+def zfpx_plan_encode_var(plan: Plan, src: torch.Tensor, maxprec: int, minexp: int,
+                         rate_cap: int, words: torch.Tensor | None = None,
+                         nd: torch.Tensor | None = None, tile_off: torch.Tensor | None = None,
+                         work: torch.Tensor | None = None, stream=None):
+    """Returns (words int32, nd uint8, tile_off int64); the stream's length is
+    tile_off[-1] words (read it after synchronising)."""
+    mw, nt, wb = zfpx_plan_var_sizes(plan, rate_cap)
+    dev = src.device
+    if words is None:
+        words = torch.empty(max(mw, 1), dtype=torch.int32, device=dev)
+    if nd is None:
+        nd = torch.empty(max(plan.nblocks, 1), dtype=torch.uint8, device=dev)
+    if tile_off is None:
+        tile_off = torch.empty(nt + 1, dtype=torch.int64, device=dev)
+    if work is None:
+        work = torch.empty((wb + 7) // 8, dtype=torch.int64, device=dev)
+    _check(_lib.zfpx_plan_encode_var(plan.handle, _dev(src, torch.float32), src.numel(),
+                                     maxprec, minexp, rate_cap, _dev(words), _nbytes(words),
+                                     _dev(nd, torch.uint8), _dev(tile_off, torch.int64),
+                                     _dev(work), _nbytes(work), _stream(stream)),
+           "zfpx_plan_encode_var")
+    return words, nd, tile_off
+
+
+def zfpx_plan_decode_var(plan: Plan, words: torch.Tensor, nd: torch.Tensor,
+                         tile_off: torch.Tensor, maxprec: int, minexp: int, rate_cap: int,
+                         dst: torch.Tensor, stream=None) -> torch.Tensor:
+    _check(_lib.zfpx_plan_decode_var(plan.handle, _dev(words), _nbytes(words),
+                                     _dev(nd, torch.uint8), _dev(tile_off, torch.int64),
+                                     maxprec, minexp, rate_cap, _dev(dst, torch.float32),
+                                     dst.numel(), _stream(stream)), "zfpx_plan_decode_var")
+    return dst
+
+
+def zfpx_plan_var_chunk_offsets(plan: Plan, nd: torch.Tensor, tile_off: torch.Tensor,
+                                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(plan.nchunks + 1, dtype=torch.int64, device=tile_off.device)
+    _check(_lib.zfpx_plan_var_chunk_offsets(plan.handle, _dev(nd, torch.uint8),
+                                            _dev(tile_off, torch.int64),
+                                            _dev(out, torch.int64), _stream(stream)),
+           "zfpx_plan_var_chunk_offsets")
+    return out
 
 
 def zfpx_plan_set_config(plan: Plan, op: int, rate: int, wg_threads: int, grid_wgs: int) -> None:

@@ -27,7 +27,9 @@ def block_families(rng, count):
             v = np.exp(rng.standard_normal(64))
         else:
             v = np.zeros(64) * (-1.0 if t % 2 else 1.0)
-        out.append(np.asarray(v, np.float32))
+        # finite inputs only (non-finite values are outside the codec's contract)
+        fmax = float(np.finfo(np.float32).max)
+        out.append(np.asarray(np.clip(v, -fmax, fmax), np.float32))
     return np.stack(out)
 
 

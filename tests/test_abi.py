@@ -12,6 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     text = open(os.path.join(ROOT, "include", "zfpx.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"^\s*#.*$", "", text, flags=re.M)  # preprocessor lines
     return sorted(set(re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\(", text)) -
                   {"sizeof", "defined"})
 
@@ -67,3 +68,32 @@ def test_plan_table_checks_without_gpu():
     # row_start must start at 0 and not decrease
     with pytest.raises(zfpx.ZfpxError):
         zfpx.Plan([0], [16], [1], [1, 2], [0, 0], [4, 4])
+
+
+def test_variable_mode_host_checks_without_gpu():
+    from paper_2609_24294_amd import zfpx
+    L = zfpx.library()
+    # minexp of accuracy mode: the largest e with 2^e <= tolerance
+    assert L.zfpx_accuracy_minexp(1.0) == 0
+    assert L.zfpx_accuracy_minexp(0.75) == -1
+    assert L.zfpx_accuracy_minexp(2.0 ** -20) == -20
+    assert L.zfpx_accuracy_minexp(1000.0) == 9
+    assert L.zfpx_accuracy_minexp(0.0) == zfpx.MINEXP_NONE
+    assert L.zfpx_accuracy_minexp(-1.0) == zfpx.MINEXP_NONE
+    fake = 4096
+    assert L.zfpx_plan_var_sizes(None, 16, None, None, None) == zfpx.EINVAL
+    p = zfpx.Plan([], [], [], [0], [], [])  # empty plan: no device tables
+    assert zfpx.zfpx_plan_var_sizes(p, 16) == (0, 0, 2 * 8)
+    for mp, me, cap in ((0, 0, 16), (33, 0, 16), (32, -1075, 16), (32, 1025, 16), (32, 0, 0),
+                        (32, 0, 33)):
+        assert L.zfpx_plan_encode_var(p.handle, fake, 0, mp, me, cap, fake, 64, fake, fake,
+                                      fake, 64, None) == zfpx.EINVAL
+        assert L.zfpx_plan_decode_var(p.handle, fake, 64, fake, fake, mp, me, cap, fake, 0,
+                                      None) == zfpx.EINVAL
+    # nothing to code: no launch
+    assert L.zfpx_plan_encode_var(p.handle, None, 0, 16, zfpx.MINEXP_NONE, 16, None, 0, None,
+                                  None, None, 0, None) == zfpx.OK
+    assert L.zfpx_plan_decode_var(p.handle, None, 0, None, None, 32, -10, 8, None, 0,
+                                  None) == zfpx.OK
+    p.close()
+
