@@ -216,7 +216,7 @@ int zfpx_accuracy_minexp(double tolerance);
 
 /* Sizes for a plan: the largest stream in 32-bit words (every block at the
  * cap), the tile count (tile_off has ntiles + 1 entries) and the bytes of the
- * encoder's scratch table.  Any pointer may be NULL. */
+ * encoder's scratch.  Any pointer may be NULL. */
 int zfpx_plan_var_sizes(const zfpx_plan* plan, int rate_cap, int64_t* max_words,
                         int64_t* ntiles, size_t* work_bytes);
 
@@ -229,11 +229,11 @@ int zfpx_plan_var_sizes(const zfpx_plan* plan, int rate_cap, int64_t* max_words,
  *   d_nd       : device, nblocks bytes.
  *   d_tile_off : device, 8-byte aligned, ntiles + 1 entries.
  *   d_work     : device scratch of at least work_bytes (ENOSPC otherwise),
- *                8-byte aligned, contents ignored: the call clears it with a
- *                kernel first.  Calls that overlap in time need separate
- *                scratch.  After the call, word 1 of the scratch is 1 if a
- *                tile waited for its predecessors beyond the kernel's bound
- *                (then the stream is invalid), else 0.
+ *                4-byte aligned, contents ignored (a staging area of
+ *                2*rate_cap words per block and one count per tile).  Calls
+ *                that overlap in time need separate scratch.
+ * Three kernels: code every tile into its staging slot, scan the tile
+ * counts, copy the tiles to their offsets.
  * Errors: EINVAL for bad parameters (maxprec 1..32, minexp
  * ZFPX_MINEXP_NONE..1024, rate_cap 1..32), null or misaligned pointers or a
  * too small source.

@@ -393,7 +393,9 @@ int zfpx_plan_var_sizes(const zfpx_plan* p, int rate_cap, int64_t* max_words, in
   if (!p || !rate_ok(rate_cap)) return ZFPX_EINVAL;
   if (max_words) *max_words = p->nblocks * 2 * rate_cap;
   if (ntiles) *ntiles = (p->nblocks + 63) / 64;
-  if (work_bytes) *work_bytes = var_table_words(p->nblocks) * sizeof(uint64_t);
+  if (work_bytes)
+    *work_bytes = (var_stage_words(p->nblocks, rate_cap) + (size_t)(p->nblocks + 63) / 64) *
+                  sizeof(uint32_t);
   return ZFPX_OK;
 }
 
@@ -404,13 +406,16 @@ int zfpx_plan_encode_var(const zfpx_plan* p, const float* d_src, int64_t src_ele
   if (!p || !var_params_ok(maxprec, minexp, rate_cap)) return ZFPX_EINVAL;
   if (p->nblocks == 0) return ZFPX_OK;
   if (!d_src || !d_words || !d_nd || !d_tile_off || !d_work || !aligned(d_words, 4) ||
-      !aligned(d_tile_off, 8) || !aligned(d_work, 8) || src_elems < p->min_elems)
+      !aligned(d_tile_off, 8) || !aligned(d_work, 4) || src_elems < p->min_elems)
     return ZFPX_EINVAL;
-  if (work_bytes < var_table_words(p->nblocks) * sizeof(uint64_t)) return ZFPX_ENOSPC;
+  const size_t stage = var_stage_words(p->nblocks, rate_cap);
+  if (work_bytes < (stage + (size_t)(p->nblocks + 63) / 64) * sizeof(uint32_t))
+    return ZFPX_ENOSPC;
   bool vec4 = p->vec4 && aligned(d_src, 16);
+  uint32_t* w = (uint32_t*)d_work;
   hipError_t e = launch_plan_encode_var(p->dev, vec4, d_src, d_words, words_bytes / 4, d_nd,
-                                        d_tile_off, (uint64_t*)d_work, rate_cap,
-                                        (int32_t)p->nblocks, maxprec, minexp, (hipStream_t)stream);
+                                        d_tile_off, w, w + stage, rate_cap, (int32_t)p->nblocks,
+                                        maxprec, minexp, (hipStream_t)stream);
   return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
 }
 

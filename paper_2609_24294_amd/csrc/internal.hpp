@@ -56,14 +56,14 @@ hipError_t launch_regular_encode(const RegularDev& g, bool vec4, const float* sr
                                  hipStream_t s);
 hipError_t launch_regular_decode(const RegularDev& g, bool vec4, const uint64_t* in, float* dst,
                                  int rate, int32_t nblocks, LaunchCfg cfg, hipStream_t s);
-// Variable-size modes over a whole plan: scratch table of var_table_words
-// 64-bit words (tile states), zeroed by the encode launch itself.
-size_t var_table_words(int64_t nblocks);
+// Variable-size modes over a whole plan: the encoder's scratch is a staging
+// area of var_stage_words 32-bit words plus one count per tile.
+size_t var_stage_words(int64_t nblocks, int cap);
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_plan_encode_var(const PlanDev& p, bool vec4, const float* src, uint32_t* out,
                                   uint64_t out_words, uint8_t* nd, int64_t* tile_off,
-                                  uint64_t* table, int cap, int32_t nblocks, int maxprec,
-                                  int minexp, hipStream_t s);
+                                  uint32_t* stage, uint32_t* tile_count, int cap,
+                                  int32_t nblocks, int maxprec, int minexp, hipStream_t s);
 hipError_t launch_plan_decode_var(const PlanDev& p, bool vec4, const uint32_t* in,
                                   uint64_t in_words, const uint8_t* nd, const int64_t* tile_off,
                                   float* dst, int cap, int32_t nblocks, int maxprec, int minexp,

@@ -435,30 +435,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // Variable-size modes (fixed precision, fixed accuracy)
 // ---------------------------------------------------------------------------
 // Block b takes nd[b] = ceil(bits / 32) 32-bit words at word offset
-// nd[0] + ... + nd[b-1].  A wavefront codes a 64-block tile as in fixed rate,
-// then needs the tile's offset: the sum of the word counts of all earlier
-// tiles.  Tiles publish their own count and then, once known, their end
-// offset in a table of 64-bit states (single-pass scan with decoupled
-// look-back): a tile sums the counts of its predecessors back to the nearest
-// one whose end offset is known.  Wavefronts take tile numbers from a counter
-// in the order they start, so every earlier tile belongs to a wavefront that
-// is running and publishes its count without waiting for anything: the wait
-// always ends.  It is also bounded: after kVarSpinLimit polls the wavefront
-// records a timeout in the table's status word and goes on.
-
-// Scratch table (zeroed before each encode): [0] tile counter, [1] status,
-// [2 + t] state of tile t: kind in bits 62-63, words in bits 0-61.
-constexpr uint64_t kVarAgg = 1ull << 62;    // the tile's own word count
-constexpr uint64_t kVarIncl = 2ull << 62;   // words of tiles 0..t (its end offset)
-constexpr uint64_t kVarValue = (1ull << 62) - 1;
-constexpr uint32_t kVarSpinLimit = 1u << 22;
-
-__device__ __forceinline__ void var_store(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t var_load(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// nd[0] + ... + nd[b-1].  A tile's offset depends on every earlier tile's
+// size, so encoding runs in three launches that never wait on each other's
+// progress: (1) each wavefront codes its 64-block tile as in fixed rate and
+// writes the tile's words, compacted, to its own staging slot of 64 * 2 * cap
+// words, plus the per-block counts and the tile's count; (2) one workgroup
+// scans the tile counts into tile offsets; (3) each wavefront copies its
+// tile's words from the staging slot to the tile's offset.  Every store of
+// the three is a contiguous 256-byte stretch per wavefront instruction.
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
 #pragma unroll
@@ -469,68 +453,24 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
   return x;
 }
 
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
-// Publish tile t's word count, find the words of all earlier tiles, publish
-// the tile's end offset; returns the tile's first word.
-__device__ __forceinline__ uint64_t var_lookback(uint64_t* table, uint32_t t, uint64_t count,
-                                                 int lane) {
-  uint64_t* state = table + 2;
-  if (t == 0) {
-    if (lane == 0) var_store(state, kVarIncl | count);
-    return 0;
-  }
-  if (lane == 0) var_store(state + t, kVarAgg | count);
-  uint64_t before = 0;
-  int64_t j = (int64_t)t - 1;  // newest tile not yet summed
-  uint32_t polls = 0;
-  for (;;) {
-    const int64_t k = j - lane;
-    const uint64_t st = k >= 0 ? var_load(state + k) : kVarIncl;
-    const uint64_t incl = __ballot((st >> 62) == 2);
-    const uint64_t none = __ballot((st >> 62) == 0);
-    const int stop = incl ? __builtin_ctzll(incl) : 63;  // lanes 0..stop are needed
-    const uint64_t need = stop == 63 ? ~0ull : ((2ull << stop) - 1);
-    if (none & need) {
-      if (++polls >= kVarSpinLimit) {
-        if (lane == 0) var_store(table + 1, 1);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    before += wave_sum64(lane <= stop ? (st & kVarValue) : 0);
-    if (incl) break;
-    j -= 64;
-  }
-  if (lane == 0) var_store(state + t, kVarIncl | (before + count));
-  return before;
-}
-
 template <int CAP, bool VEC4, class Geo>
 __global__ __launch_bounds__(256) void k_encode_var(Geo geo, const float* __restrict__ src,
-                                                    uint32_t* __restrict__ out, uint64_t out_words,
-                                                    uint8_t* __restrict__ nd_out,
-                                                    int64_t* __restrict__ tile_off,
-                                                    uint64_t* table, int cap_rt, int32_t nblocks,
-                                                    int maxprec, int minexp) {
+                                                    uint32_t* __restrict__ stage,
+                                                    uint32_t* __restrict__ tile_count,
+                                                    uint8_t* __restrict__ nd_out, int cap_rt,
+                                                    int32_t nblocks, int maxprec, int minexp) {
   extern __shared__ uint64_t lds[];
   const int cap = CAP > 0 ? CAP : cap_rt;
   const int stride = lds_stride(cap);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint64_t* slice = lds + (size_t)(wave * 64 + lane) * stride;
-  const uint32_t ntiles = (uint32_t)(nblocks + 63) >> 6;
-  uint32_t t = 0;
-  if (lane == 0)
-    t = (uint32_t)__hip_atomic_fetch_add(table, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  t = __builtin_amdgcn_readfirstlane(t);
+  const int waves = blockDim.x >> 6;
+  uint64_t* wlds = lds + (size_t)wave * 64 * stride;
+  uint64_t* slice = wlds + lane * stride;
+  const int32_t ntiles = (nblocks + 63) >> 6;
+  const int32_t t = blockIdx.x * waves + wave;
   if (t >= ntiles) return;
-  const int32_t b0 = (int32_t)(t << 6);
+  const int32_t b0 = t << 6;
   const int nact = nblocks - b0 < 64 ? nblocks - b0 : 64;
   for (int i = 0; i < stride; i++) slice[i] = 0;
   uint32_t bits = 0;
@@ -543,18 +483,74 @@ __global__ __launch_bounds__(256) void k_encode_var(Geo geo, const float* __rest
   }
   const uint32_t nd = (bits + 31) >> 5;
   if (lane < nact) nd_out[b0 + lane] = (uint8_t)nd;
-  const uint32_t incl = wave_incl_scan(nd, lane);
-  const uint32_t count = __builtin_amdgcn_readlane(incl, 63);
-  const uint64_t first = var_lookback(table, t, count, lane);
-  if (lane == 0) {
-    tile_off[t] = (int64_t)first;
-    if (t == ntiles - 1) tile_off[ntiles] = (int64_t)(first + count);
-  }
+  const uint32_t excl = wave_incl_scan(nd, lane) - nd;
+  const uint32_t count = __builtin_amdgcn_readlane(excl + nd, 63);
+  if (lane == 0) tile_count[t] = count;
   wave_sync_lds();
-  const uint32_t* s32 = reinterpret_cast<const uint32_t*>(slice);
-  const uint64_t o = first + (incl - nd);
-  for (uint32_t i = 0; i < nd; i++)
-    if (o + i < out_words) out[o + i] = s32[i];
+  // word q of the tile belongs to the last block whose first word is <= q
+  // (blocks have at least one word; lanes past the tile start at `count`)
+  const uint32_t* w32 = reinterpret_cast<const uint32_t*>(wlds);
+  uint32_t* out = stage + (size_t)t * 64 * 2 * cap;
+  for (uint32_t q0 = 0; q0 < count; q0 += 64) {
+    const uint32_t q = q0 + lane;
+    int lo = 0;
+    uint32_t elo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      const uint32_t e = __shfl(excl, lo + step, 64);
+      if (e <= q) {
+        lo += step;
+        elo = e;
+      }
+    }
+    if (q < count) out[q] = w32[(uint32_t)lo * 2 * stride + (q - elo)];
+  }
+}
+
+// Tile offsets: exclusive prefix sums of the tile counts, and the total.
+__global__ __launch_bounds__(1024) void k_var_scan(const uint32_t* __restrict__ tile_count,
+                                                   int32_t ntiles, int64_t* __restrict__ tile_off) {
+  __shared__ int64_t part[1024];
+  const int i = threadIdx.x;
+  const int32_t per = (ntiles + 1023) / 1024;
+  const int32_t k0 = i * per < ntiles ? i * per : ntiles;
+  const int32_t k1 = k0 + per < ntiles ? k0 + per : ntiles;
+  int64_t sum = 0;
+  for (int32_t k = k0; k < k1; k++) sum += tile_count[k];
+  part[i] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t y = i >= o ? part[i - o] : 0;
+    __syncthreads();
+    part[i] += y;
+    __syncthreads();
+  }
+  int64_t run = part[i] - sum;
+  for (int32_t k = k0; k < k1; k++) {
+    tile_off[k] = run;
+    run += tile_count[k];
+  }
+  if (i == 1023) tile_off[ntiles] = part[1023];
+}
+
+// Copy each tile's words from its staging slot to its offset; words at or
+// past out_words are not written.
+__global__ __launch_bounds__(256) void k_var_place(const uint32_t* __restrict__ stage,
+                                                   const uint32_t* __restrict__ tile_count,
+                                                   const int64_t* __restrict__ tile_off,
+                                                   int32_t ntiles, int cap,
+                                                   uint32_t* __restrict__ out,
+                                                   uint64_t out_words) {
+  const int lane = threadIdx.x & 63;
+  const int waves = blockDim.x >> 6;
+  const int32_t t = blockIdx.x * waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (t >= ntiles) return;
+  const uint32_t count = uniform_load(tile_count, t);
+  const uint64_t o = (uint64_t)uniform_load(tile_off, t);
+  const uint32_t* in = stage + (size_t)t * 64 * 2 * cap;
+#pragma unroll 4
+  for (uint32_t q = lane; q < count; q += 64)
+    if (o + q < out_words) out[o + q] = in[q];
 }
 
 // Any content of the stream, counts and offsets decodes without a fault:
@@ -1110,7 +1106,9 @@ hipError_t launch_f16_restore(const uint16_t* in, size_t n, float* out, hipStrea
       break;                                                                       \
   }
 
-size_t var_table_words(int64_t nblocks) { return (size_t)((nblocks + 63) >> 6) + 2; }
+size_t var_stage_words(int64_t nblocks, int cap) {
+  return (size_t)((nblocks + 63) >> 6) * 64 * 2 * (size_t)cap;
+}
 
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -1121,23 +1119,28 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
 
 hipError_t launch_plan_encode_var(const PlanDev& p, bool vec4, const float* src, uint32_t* out,
                                   uint64_t out_words, uint8_t* nd, int64_t* tile_off,
-                                  uint64_t* table, int cap, int32_t nblocks, int maxprec,
-                                  int minexp, hipStream_t s) {
+                                  uint32_t* stage, uint32_t* tile_count, int cap,
+                                  int32_t nblocks, int maxprec, int minexp, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  hipError_t e = launch_fill_u64(table, (int64_t)var_table_words(nblocks), 0, s);
-  if (e != hipSuccess) return e;
   constexpr int wg = 128;
   const int ntiles = (nblocks + 63) >> 6;
   dim3 grid((ntiles + wg / 64 - 1) / (wg / 64)), block(wg);
   size_t shm = lds_bytes(wg, cap);
   PlanGeo geo{p};
   if (vec4) {
-    ZFPX_CAP_SWITCH(k_encode_var, PlanGeo, true, geo, src, out, out_words, nd, tile_off, table,
-                    cap, nblocks, maxprec, minexp);
+    ZFPX_CAP_SWITCH(k_encode_var, PlanGeo, true, geo, src, stage, tile_count, nd, cap, nblocks,
+                    maxprec, minexp);
   } else {
-    ZFPX_CAP_SWITCH(k_encode_var, PlanGeo, false, geo, src, out, out_words, nd, tile_off, table,
-                    cap, nblocks, maxprec, minexp);
+    ZFPX_CAP_SWITCH(k_encode_var, PlanGeo, false, geo, src, stage, tile_count, nd, cap, nblocks,
+                    maxprec, minexp);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_var_scan, dim3(1), dim3(1024), 0, s, tile_count, ntiles, tile_off);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_var_place, dim3((ntiles + 3) / 4), dim3(256), 0, s, stage, tile_count,
+                     tile_off, ntiles, cap, out, out_words);
   return hipGetLastError();
 }
 

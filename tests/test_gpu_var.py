@@ -132,7 +132,6 @@ def test_scratch_reused_across_calls(zfpx_lib):
         gw, gnd, gtoff = _stream(words, nd, toff)
         ow, ond, otoff = oracle.pack_encode_var(cs, a, maxprec, minexp, cap)
         assert np.array_equal(gw, ow) and np.array_equal(gtoff, otoff)
-        assert int(work[1].item()) == 0  # no wait ran into its bound
 
 
 def test_decoder_on_arbitrary_content(zfpx_lib):
