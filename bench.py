@@ -82,6 +82,8 @@ def parse():
                     help="skip the O2560 x 90 levels (9.47 GB) throughput leg")
     ap.add_argument("--no-variable", action="store_true",
                     help="skip the fixed-precision / fixed-accuracy leg")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip the chunk-pipelined send/receive over a host link")
     ap.add_argument("--serving-requests", type=int, default=10000)
     return ap.parse_args()
 
@@ -205,6 +207,10 @@ def main():
         variable = variable_report(plan, src, dst, nvals, nblocks, max(5, args.steps // 2),
                                    torch, zfpx, W)
 
+    pipeline = None
+    if not args.no_pipeline:
+        pipeline = pipeline_report(plan, src[0], nvals, nblocks, torch, zfpx)
+
     accuracy = None
     if not args.no_accuracy:
         accuracy = accuracy_report(plan, src[0], dst[0], nvals, nblocks, torch, zfpx, W)
@@ -272,6 +278,7 @@ def main():
         **extras,
         "accuracy": accuracy,
         "variable": variable,
+        "pipeline": pipeline,
         "large": large,
         "batching": batching,
         "serving": serving,
@@ -335,6 +342,87 @@ def variable_report(plan, src, dst, nvals, nblocks, steps, torch, zfpx, W):
             r["tolerance"] = 1e-2
         out[name] = r
         del sets
+    return out
+
+
+def pipeline_report(plan, src, nvals, nblocks, torch, zfpx, reps=5):
+    """Send (encode + device-to-host copy) and receive (host-to-device copy +
+    decode) of the share over a host link on two streams: float32 and float16
+    copies, fixed rate 16 with the whole buffer coded before the copy (the
+    paper's serial model) and with the copy of chunk group g overlapping the
+    coding of group g+1.  Times from the first enqueue to the end of both
+    streams (HIP events); inputs resident in HBM, host buffers pinned."""
+    cs, xs = torch.cuda.Stream(), torch.cuda.Stream()
+    log("pipeline: float32 / float16 / rate 16 serial and chunk-pipelined over a host link")
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(cs)
+            xs.wait_event(e0)
+            fn()
+            cs.wait_stream(xs)
+            e1.record(cs)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return min(ts[1:])
+
+    dev = src.device
+    link32 = torch.empty(nvals, dtype=torch.float32).pin_memory()
+    out = {"link": "device <-> pinned host memory (PCIe) standing in for the network; two streams",
+           "chunks": plan.nchunks}
+
+    def f32_send():
+        with torch.cuda.stream(xs):
+            link32.copy_(src, non_blocking=True)
+
+    dst = torch.empty_like(src)
+
+    def f32_recv():
+        with torch.cuda.stream(xs):
+            dst.copy_(link32, non_blocking=True)
+
+    t32s, t32r = timed(f32_send), timed(f32_recv)
+    out["float32"] = {"send_ms": round(t32s, 3), "recv_ms": round(t32r, 3),
+                      "link_gbs_d2h": round(4 * nvals / (t32s * 1e-3) / 1e9, 1),
+                      "link_gbs_h2d": round(4 * nvals / (t32r * 1e-3) / 1e9, 1)}
+    h16 = torch.empty(nvals, dtype=torch.int16, device=dev)
+    link16 = torch.empty(nvals, dtype=torch.int16).pin_memory()
+
+    def f16_send():
+        with torch.cuda.stream(cs):
+            zfpx.f16_truncate(src, h16, stream=cs)
+        xs.wait_stream(cs)
+        with torch.cuda.stream(xs):
+            link16.copy_(h16, non_blocking=True)
+
+    def f16_recv():
+        with torch.cuda.stream(xs):
+            h16.copy_(link16, non_blocking=True)
+        cs.wait_stream(xs)
+        zfpx.f16_restore(h16, dst, stream=cs)
+
+    t16s, t16r = timed(f16_send), timed(f16_recv)
+    out["float16"] = {"send_ms": round(t16s, 3), "recv_ms": round(t16r, 3),
+                      "speedup_send": round(t32s / t16s, 3), "speedup_recv": round(t32r / t16r, 3)}
+    del h16, link16
+    for rate in (16, 8):
+        nbytes = nblocks * 8 * rate
+        send = torch.empty(nbytes // 8, dtype=torch.int64, device=dev)
+        recv = torch.empty_like(send)
+        link = torch.empty(nbytes // 8, dtype=torch.int64).pin_memory()
+        for groups in (1, 8, 16, 64):
+            pipe = zfpx.Pipeline(plan, rate, groups)
+            ts = timed(lambda: pipe.send(src, send, link, cs, xs))
+            tr = timed(lambda: pipe.recv(link, recv, dst, cs, xs))
+            out[f"rate{rate}_groups{groups}"] = {
+                "send_ms": round(ts, 3), "recv_ms": round(tr, 3),
+                "speedup_send": round(t32s / ts, 3), "speedup_recv": round(t32r / tr, 3),
+                "speedup_round_trip": round((t32s + t32r) / (ts + tr), 3)}
+            pipe.close()
+        del send, recv, link
     return out
 
 

@@ -182,6 +182,41 @@ int zfpx_decode_unpack_chunks(const zfpx_plan* plan, int32_t first, int32_t coun
                               int64_t dst_elems, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Chunk-wise pipeline over a link
+ * ---------------------------------------------------------------------- */
+
+/*
+ * The paper adds codec time before and after the exchange (t_compress +
+ * t_comm + t_decompress) and notes that compressing and sending could be
+ * pipelined (Section III-D).  A pipeline cuts the plan's chunks into `groups`
+ * consecutive groups (fewer if there are fewer chunks):
+ *   send: group g is encoded on compute_stream, then copied device -> host
+ *         (h_link, at the group's offset in the fixed-rate stream) on
+ *         copy_stream, so the copy of group g overlaps the encoding of g+1;
+ *   recv: group g is copied host -> device on copy_stream, then decoded on
+ *         compute_stream while group g+1 is being copied.
+ * The host buffer stands in for the link on a single GPU (host memory over
+ * PCIe); h_link must be pinned (hipHostMalloc) for the copies to be
+ * asynchronous.  Both streams must be distinct; calls only enqueue (no
+ * synchronisation): the send's bytes are in h_link once copy_stream reaches
+ * the call's end, the recv's floats once compute_stream does.
+ * zfpx_pipeline_create creates 2*groups HIP events (call it outside hot
+ * loops); a pipeline refers to its plan, which must outlive it.
+ * Errors: EINVAL (null pointers, bad rate or groups < 1), ENOSPC (a buffer
+ * smaller than the coded size), the errors of the range calls.
+ */
+typedef struct zfpx_pipeline zfpx_pipeline;
+
+int zfpx_pipeline_create(const zfpx_plan* plan, int rate, int32_t groups, zfpx_pipeline** out);
+int zfpx_pipeline_send(zfpx_pipeline* pipe, const float* d_src, int64_t src_elems, void* d_send,
+                       size_t send_bytes, void* h_link, size_t link_bytes, void* compute_stream,
+                       void* copy_stream);
+int zfpx_pipeline_recv(zfpx_pipeline* pipe, const void* h_link, size_t link_bytes, void* d_recv,
+                       size_t recv_bytes, float* d_dst, int64_t dst_elems, void* compute_stream,
+                       void* copy_stream);
+int zfpx_pipeline_destroy(zfpx_pipeline* pipe);
+
+/* -------------------------------------------------------------------------
  * Variable-size modes: fixed precision and fixed accuracy
  * ---------------------------------------------------------------------- */
 

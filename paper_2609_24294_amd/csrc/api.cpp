@@ -373,6 +373,106 @@ int zfpx_decode_unpack_chunks(const zfpx_plan* p, int32_t first, int32_t count,
 }
 
 // ---------------------------------------------------------------------------
+// Chunk-wise pipeline over a link
+// ---------------------------------------------------------------------------
+
+struct zfpx_pipeline {
+  const zfpx_plan* plan = nullptr;
+  int rate = 0;
+  std::vector<int32_t> first;          // group g = chunks [first[g], first[g + 1])
+  std::vector<hipEvent_t> sent, recvd;  // per group
+};
+
+int zfpx_pipeline_destroy(zfpx_pipeline* pp) {
+  if (!pp) return ZFPX_EINVAL;
+  for (hipEvent_t e : pp->sent)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : pp->recvd)
+    if (e) (void)hipEventDestroy(e);
+  delete pp;
+  return ZFPX_OK;
+}
+
+int zfpx_pipeline_create(const zfpx_plan* p, int rate, int32_t groups, zfpx_pipeline** out) {
+  if (!p || !out || !rate_ok(rate) || groups < 1) return ZFPX_EINVAL;
+  *out = nullptr;
+  const int32_t g = std::min<int32_t>(groups, std::max<int32_t>(p->nchunks, 1));
+  zfpx_pipeline* pp = new (std::nothrow) zfpx_pipeline();
+  if (!pp) return ZFPX_ENOMEM;
+  pp->plan = p;
+  pp->rate = rate;
+  pp->first.resize(g + 1);
+  for (int32_t i = 0; i <= g; i++) pp->first[i] = (int32_t)((int64_t)i * p->nchunks / g);
+  pp->sent.assign(g, nullptr);
+  pp->recvd.assign(g, nullptr);
+  for (int32_t i = 0; i < g; i++) {
+    if (hipEventCreateWithFlags(&pp->sent[i], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pp->recvd[i], hipEventDisableTiming) != hipSuccess) {
+      zfpx_pipeline_destroy(pp);
+      return ZFPX_EHIP;
+    }
+  }
+  *out = pp;
+  return ZFPX_OK;
+}
+
+// Byte range of group i's chunks in a fixed-rate stream.
+static void group_bytes(const zfpx_pipeline* pp, size_t i, size_t* off, size_t* bytes) {
+  const zfpx_plan* p = pp->plan;
+  const int64_t b0 = p->chunk_first[pp->first[i]], b1 = p->chunk_first[pp->first[i + 1]];
+  *off = (size_t)b0 * 8 * pp->rate;
+  *bytes = (size_t)(b1 - b0) * 8 * pp->rate;
+}
+
+int zfpx_pipeline_send(zfpx_pipeline* pp, const float* d_src, int64_t src_elems, void* d_send,
+                       size_t send_bytes, void* h_link, size_t link_bytes, void* compute_stream,
+                       void* copy_stream) {
+  if (!pp || !d_send || !h_link) return ZFPX_EINVAL;
+  const size_t total = (size_t)pp->plan->nblocks * 8 * pp->rate;
+  if (send_bytes < total || link_bytes < total) return ZFPX_ENOSPC;
+  hipStream_t cs = (hipStream_t)compute_stream, xs = (hipStream_t)copy_stream;
+  for (size_t i = 0; i + 1 < pp->first.size(); i++) {
+    const int32_t c0 = pp->first[i], n = pp->first[i + 1] - c0;
+    int st = zfpx_pack_encode_chunks(pp->plan, c0, n, d_src, src_elems, pp->rate, d_send,
+                                     send_bytes, cs);
+    if (st) return st;
+    size_t off, bytes;
+    group_bytes(pp, i, &off, &bytes);
+    if (bytes == 0) continue;
+    if (hipEventRecord(pp->sent[i], cs) != hipSuccess ||
+        hipStreamWaitEvent(xs, pp->sent[i], 0) != hipSuccess ||
+        hipMemcpyAsync((char*)h_link + off, (const char*)d_send + off, bytes,
+                       hipMemcpyDeviceToHost, xs) != hipSuccess)
+      return ZFPX_EHIP;
+  }
+  return ZFPX_OK;
+}
+
+int zfpx_pipeline_recv(zfpx_pipeline* pp, const void* h_link, size_t link_bytes, void* d_recv,
+                       size_t recv_bytes, float* d_dst, int64_t dst_elems, void* compute_stream,
+                       void* copy_stream) {
+  if (!pp || !d_recv || !h_link) return ZFPX_EINVAL;
+  const size_t total = (size_t)pp->plan->nblocks * 8 * pp->rate;
+  if (recv_bytes < total || link_bytes < total) return ZFPX_ENOSPC;
+  hipStream_t cs = (hipStream_t)compute_stream, xs = (hipStream_t)copy_stream;
+  for (size_t i = 0; i + 1 < pp->first.size(); i++) {
+    const int32_t c0 = pp->first[i], n = pp->first[i + 1] - c0;
+    size_t off, bytes;
+    group_bytes(pp, i, &off, &bytes);
+    if (bytes == 0) continue;
+    if (hipMemcpyAsync((char*)d_recv + off, (const char*)h_link + off, bytes,
+                       hipMemcpyHostToDevice, xs) != hipSuccess ||
+        hipEventRecord(pp->recvd[i], xs) != hipSuccess ||
+        hipStreamWaitEvent(cs, pp->recvd[i], 0) != hipSuccess)
+      return ZFPX_EHIP;
+    int st = zfpx_decode_unpack_chunks(pp->plan, c0, n, d_recv, recv_bytes, pp->rate, d_dst,
+                                       dst_elems, cs);
+    if (st) return st;
+  }
+  return ZFPX_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Variable-size modes
 // ---------------------------------------------------------------------------
 

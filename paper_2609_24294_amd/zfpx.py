@@ -65,6 +65,10 @@ _SIGS = {
     "zfpx_server_destroy": (_INT, [_P]),
     "zfpx_server_replay": (_INT, [_P, _P, _P, _I64, _c.c_double, _P]),
     "zfpx_plain_replay": (_INT, [_P, _P, _I64, _c.c_double, _P, _P]),
+    "zfpx_pipeline_create": (_INT, [_P, _INT, _I32, _c.POINTER(_P)]),
+    "zfpx_pipeline_send": (_INT, [_P, _P, _I64, _P, _SZ, _P, _SZ, _P, _P]),
+    "zfpx_pipeline_recv": (_INT, [_P, _P, _SZ, _P, _SZ, _P, _I64, _P, _P]),
+    "zfpx_pipeline_destroy": (_INT, [_P]),
     "zfpx_accuracy_minexp": (_INT, [_c.c_double]),
     "zfpx_plan_var_sizes": (_INT, [_P, _INT, _PI64, _PI64, _c.POINTER(_SZ)]),
     "zfpx_plan_encode_var": (_INT, [_P, _P, _I64, _INT, _INT, _INT, _P, _SZ, _P, _P, _P, _SZ,
@@ -263,6 +267,55 @@ def zfpx_decode_unpack_chunks(plan: Plan, first: int, count: int, recv: torch.Te
                                           rate, _dev(dst, torch.float32), dst.numel(),
                                           _stream(stream)), "zfpx_decode_unpack_chunks")
     return dst
+
+
+# ---------------------------------------------------------------------------
+# Chunk-wise pipeline over a link (host memory standing in for it)
+# ---------------------------------------------------------------------------
+
+class Pipeline:
+    """zfpx_pipeline_*: encode chunk groups on one stream while the previous
+    group is copied to pinned host memory on another (and the reverse)."""
+
+    def __init__(self, plan: Plan, rate: int, groups: int):
+        self.plan, self.rate = plan, rate
+        h = _P()
+        _check(_lib.zfpx_pipeline_create(plan.handle, rate, groups, _c.byref(h)),
+               "zfpx_pipeline_create")
+        self._h = h
+
+    def send(self, src: torch.Tensor, send: torch.Tensor, link: torch.Tensor,
+             compute_stream, copy_stream) -> None:
+        if link.is_cuda or not link.is_pinned():
+            raise ValueError("link must be pinned host memory")
+        _check(_lib.zfpx_pipeline_send(self._h, _dev(src, torch.float32), src.numel(),
+                                       _dev(send), _nbytes(send), link.data_ptr(), _nbytes(link),
+                                       _stream(compute_stream), _stream(copy_stream)),
+               "zfpx_pipeline_send")
+
+    def recv(self, link: torch.Tensor, recv: torch.Tensor, dst: torch.Tensor,
+             compute_stream, copy_stream) -> None:
+        if link.is_cuda or not link.is_pinned():
+            raise ValueError("link must be pinned host memory")
+        _check(_lib.zfpx_pipeline_recv(self._h, link.data_ptr(), _nbytes(link), _dev(recv),
+                                       _nbytes(recv), _dev(dst, torch.float32), dst.numel(),
+                                       _stream(compute_stream), _stream(copy_stream)),
+               "zfpx_pipeline_recv")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.zfpx_pipeline_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def zfpx_pipeline_create(plan: Plan, rate: int, groups: int) -> Pipeline:
+    return Pipeline(plan, rate, groups)
 
 
 # ---------------------------------------------------------------------------

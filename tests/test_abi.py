@@ -97,3 +97,18 @@ def test_variable_mode_host_checks_without_gpu():
                                   None) == zfpx.OK
     p.close()
 
+
+
+def test_pipeline_host_checks_without_gpu():
+    from paper_2609_24294_amd import zfpx
+    L = zfpx.library()
+    import ctypes
+    h = ctypes.c_void_p()
+    assert L.zfpx_pipeline_create(None, 16, 4, ctypes.byref(h)) == zfpx.EINVAL
+    p = zfpx.Plan([], [], [], [0], [], [])
+    assert L.zfpx_pipeline_create(p.handle, 0, 4, ctypes.byref(h)) == zfpx.EINVAL
+    assert L.zfpx_pipeline_create(p.handle, 16, 0, ctypes.byref(h)) == zfpx.EINVAL
+    assert L.zfpx_pipeline_send(None, None, 0, None, 0, None, 0, None, None) == zfpx.EINVAL
+    assert L.zfpx_pipeline_recv(None, None, 0, None, 0, None, 0, None, None) == zfpx.EINVAL
+    assert L.zfpx_pipeline_destroy(None) == zfpx.EINVAL
+    p.close()
