@@ -171,6 +171,9 @@ SMALL = dict(nlev=8, nlat=64, nlon=128)
 ZLAMBDA = dict(nfields=4, nlev=137, nrows=64, npts=1612, nchunks=64, row0=1024, n_half=1280)
 LTHETA = dict(n_half=1280, nlev=137, nchunks=256)
 LARGE = dict(n_half=2560, nlev=90, nchunks=1)
+# lambda->theta in Fourier space: rows 1024..1087 of O1280 (all hold 4116+ points,
+# so every wavenumber up to the TCo1279 truncation), 137 levels, 16 destinations
+FOURIER = dict(nlev=137, nrows=64, mmax=1279, ndest=16, row0=1024, n_half=1280)
 
 
 def small_chunkset() -> ChunkSet:
@@ -179,6 +182,19 @@ def small_chunkset() -> ChunkSet:
 
 def ltheta_chunkset() -> ChunkSet:
     return reduced_grid_chunkset(LTHETA["n_half"], LTHETA["nlev"], LTHETA["nchunks"])
+
+
+def fourier_buffer(L: int | None = None, nlev: int | None = None, nrows: int | None = None):
+    """The Fourier-space lambda->theta share: (f32 planes [2][nlev][nrows][L+1],
+    float64 planes) from T-field coefficients at Gauss latitudes row0.. of
+    O1280 (seed of config 6)."""
+    c = FOURIER
+    L = c["mmax"] if L is None else L
+    nlev = c["nlev"] if nlev is None else nlev
+    nrows = c["nrows"] if nrows is None else nrows
+    mu = gaussian_mu(2 * c["n_half"])[c["row0"]:c["row0"] + nrows]
+    F = fourier_share(L, mu, nlev, seed_for(6, FIELD_IDS["T"]))
+    return fourier_planes(F)
 
 
 def large_chunkset() -> ChunkSet:
@@ -252,6 +268,80 @@ def fourier_coefficients(L: int, mu: np.ndarray, nlev: int, seed: int, rho: floa
         P = _legendre_m(L, m, mu, pmm)
         F[m] = P @ A[m]
     return F
+
+
+def _ar1(x: np.ndarray, rho: float, gain: float) -> np.ndarray:
+    """y[k] = rho y[k-1] + gain x[k] along axis 0, y[-1] = 0."""
+    try:
+        from scipy.signal import lfilter
+        return lfilter([gain], [1.0, -rho], x, axis=0)
+    except ImportError:  # pragma: no cover
+        y = np.empty_like(x)
+        y[0] = gain * x[0]
+        for k in range(1, x.shape[0]):
+            y[k] = rho * y[k - 1] + gain * x[k]
+        return y
+
+
+def fourier_share(L: int, mu: np.ndarray, nlev: int, seed: int, rho: float = 0.9) -> np.ndarray:
+    """Fourier coefficients F[level, row, m] (m = 0..L, complex128) of a random
+    spherical-harmonic field on the given latitude rows: what a row FFT of the
+    grid field yields before the Legendre transform.
+
+    a_lm are complex Gaussian with E|a_lm|^2 = (l+1)^-3 (real for m = 0),
+    AR(1) from level to level with coefficient rho; generated one wavenumber
+    at a time (innovations (l, level) per m), so any truncation L fits in
+    memory.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    F = np.zeros((nlev, mu.size, L + 1), np.complex128)
+    innov = math.sqrt(1.0 - rho * rho)
+    sin_t = np.sqrt(np.maximum(0.0, 1.0 - mu * mu))
+    pmm = np.full(mu.size, 1.0 / math.sqrt(4.0 * math.pi))
+    for m in range(L + 1):
+        if m > 0:
+            pmm = math.sqrt((2.0 * m + 1.0) / (2.0 * m)) * sin_t * pmm
+        nl = L - m + 1
+        sd = (np.arange(m, L + 1) + 1.0) ** -1.5
+        if m == 0:
+            xi = rng.standard_normal((nlev, nl)) * sd
+        else:
+            xi = (rng.standard_normal((nlev, nl)) + 1j * rng.standard_normal((nlev, nl))) \
+                * (sd / math.sqrt(2))
+        xi[0] /= innov  # A[0] = xi[0], then A[k] = rho A[k-1] + innov xi[k]
+        A = _ar1(xi, rho, innov)
+        P = _legendre_m(L, m, mu, pmm)          # (rows, l)
+        F[:, :, m] = A @ P.T                    # (levels, rows)
+    return F
+
+
+def fourier_chunkset(nlev: int, nrows: int, mmax: int, ndest: int) -> ChunkSet:
+    """The lambda->theta send buffer in Fourier space: f32[2][nlev][nrows][mmax+1]
+    (real plane, then imaginary plane; m fastest).  Destination d gets the
+    wavenumbers m0..m1-1, m0 = floor((mmax+1) d / ndest), of every row and
+    level: its message is two chunks, the real one then the imaginary one."""
+    M = mmax + 1
+    plane = nlev * nrows * M
+    base, rs, offs, lens = [], [0], [], []
+    for d in range(ndest):
+        m0, m1 = (M * d) // ndest, (M * (d + 1)) // ndest
+        for part in (0, 1):
+            base.append(part * plane + m0)
+            offs.append(np.arange(nrows, dtype=np.int64) * M)
+            lens.append(np.full(nrows, m1 - m0))
+            rs.append(rs[-1] + nrows)
+    n = 2 * ndest
+    return ChunkSet(np.array(base), np.full(n, nrows * M), np.full(n, nlev), np.array(rs),
+                    np.concatenate(offs), np.concatenate(lens), 2 * plane)
+
+
+def fourier_planes(F: np.ndarray) -> np.ndarray:
+    """Real and imaginary planes f32[2][nlev][nrows][mmax+1], scaled so that the
+    whole buffer has unit RMS (the float64 planes before rounding are
+    returned too)."""
+    planes = np.stack([F.real, F.imag])
+    planes = planes / math.sqrt(float(np.mean(planes * planes)))
+    return planes.astype(np.float32), planes
 
 
 def _irfft(c: np.ndarray, n: int) -> np.ndarray:
