@@ -84,6 +84,8 @@ def parse():
                     help="skip the fixed-precision / fixed-accuracy leg")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the chunk-pipelined send/receive over a host link")
+    ap.add_argument("--no-fourier", action="store_true",
+                    help="skip the Fourier-space lambda->theta buffer leg")
     ap.add_argument("--serving-requests", type=int, default=10000)
     return ap.parse_args()
 
@@ -211,6 +213,10 @@ def main():
     if not args.no_pipeline:
         pipeline = pipeline_report(plan, src[0], nvals, nblocks, torch, zfpx)
 
+    fourier = None
+    if not args.no_fourier:
+        fourier = fourier_report(max(5, args.steps // 2), torch, zfpx, W)
+
     accuracy = None
     if not args.no_accuracy:
         accuracy = accuracy_report(plan, src[0], dst[0], nvals, nblocks, torch, zfpx, W)
@@ -279,6 +285,7 @@ def main():
         "accuracy": accuracy,
         "variable": variable,
         "pipeline": pipeline,
+        "fourier": fourier,
         "large": large,
         "batching": batching,
         "serving": serving,
@@ -423,6 +430,80 @@ def pipeline_report(plan, src, nvals, nblocks, torch, zfpx, reps=5):
                 "speedup_round_trip": round((t32s + t32r) / (ts + tr), 3)}
             pipe.close()
         del send, recv, link
+    return out
+
+
+def fourier_report(steps, torch, zfpx, W, nsets=3):
+    """The lambda->theta share in Fourier space (real and imaginary planes of
+    T1279 coefficients, 2 x 137 x 64 x 1280 f32, 32 chunks): encode/decode
+    time at rates 16 and 8 and in the variable-size modes (HIP events), and
+    the error of each against the FP64 coefficients, with float16 beside."""
+    import numpy as np
+
+    from paper_2609_24294_amd import metrics
+    c = W.FOURIER
+    log("fourier: generating the T1279 Fourier-space share (2 x 137 x 64 x 1280)")
+    f32, f64 = W.fourier_buffer()
+    cs = W.fourier_chunkset(c["nlev"], c["nrows"], c["mmax"], c["ndest"])
+    plan = zfpx.Plan.from_chunkset(cs)
+    nvals, nblocks = f32.size, plan.nblocks
+    dev = torch.device("cuda:0")
+    src = [torch.from_numpy(f32.reshape(-1)).to(dev) for _ in range(nsets)]
+    dst = [torch.empty_like(src[0]) for _ in range(nsets)]
+    ref = np.sqrt((f64 * f64).sum())
+
+    def errors(back):
+        back = back.reshape(f64.shape)
+        d = back.astype(np.float64) - f64
+        r = {"global": float(f"{np.sqrt((d * d).sum()) / ref:.3e}")}
+        for k, name in ((0, "real"), (1, "imag")):
+            e = metrics.error_report(f64[k], back[k], pointwise=False)
+            r[name] = {"block_mean": float(f"{e['block_mean']:.3e}"),
+                       "block_max": float(f"{e['block_max']:.3e}")}
+        return r
+
+    out = {"workload": "Fourier-space lambda->theta share: T1279 coefficients of T on rows "
+                       "1024..1087 of O1280, 137 levels, real and imaginary planes, 16 destinations "
+                       "x 2 chunks (synthetic, (l+1)^-3 spectrum)",
+           "values": nvals, "blocks": nblocks}
+    for rate in (16, 8):
+        send = [torch.empty(nblocks * rate, dtype=torch.int64, device=dev) for _ in range(nsets)]
+        enc = lambda i: zfpx.zfpx_pack_encode(plan, src[i % nsets], rate, send[i % nsets])
+        dec = lambda i: zfpx.zfpx_decode_unpack(plan, send[i % nsets], rate, dst[i % nsets])
+        _, (te, td) = timed_loop([enc, dec], steps, 2, torch)
+        zfpx.zfpx_decode_unpack(plan, send[0], rate, dst[0])
+        alg = 4 * nvals + nblocks * 8 * rate
+        out[f"rate{rate}"] = {"encode_ms": round(te, 4), "decode_ms": round(td, 4),
+                              "encode_hbm_frac": round(alg / (te * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "decode_hbm_frac": round(alg / (td * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "bytes_reduction": round(4 * nvals / (nblocks * 8 * rate), 3),
+                              **errors(dst[0].cpu().numpy())}
+        del send
+    h = zfpx.f16_truncate(src[0])
+    out["f16"] = {"bytes_reduction": 2.0, **errors(zfpx.f16_restore(h).cpu().numpy())}
+    ntiles = (nblocks + 63) // 64
+    for name, maxprec, minexp, cap in (("precision16", 16, zfpx.MINEXP_NONE, 16),
+                                       ("accuracy_1e-4", 32, zfpx.zfpx_accuracy_minexp(1e-4), 32)):
+        sets = [zfpx.zfpx_plan_encode_var(plan, src[i], maxprec, minexp, cap) for i in range(nsets)]
+        enc = lambda i: zfpx.zfpx_plan_encode_var(plan, src[i % nsets], maxprec, minexp, cap,
+                                                  *sets[i % nsets])
+        dec = lambda i: zfpx.zfpx_plan_decode_var(plan, *sets[i % nsets], maxprec, minexp, cap,
+                                                  dst[i % nsets])
+        _, (te, td) = timed_loop([enc, dec], steps, 2, torch)
+        torch.cuda.synchronize()
+        w, nd, to = sets[0]
+        zfpx.zfpx_plan_decode_var(plan, w, nd, to, maxprec, minexp, cap, dst[0])
+        words = int(to[-1].item())
+        index = nblocks + 8 * (ntiles + 1)
+        back = dst[0].cpu().numpy()
+        r = {"encode_ms": round(te, 4), "decode_ms": round(td, 4),
+             "bits_per_value": round(8 * (4 * words + index) / nvals, 3),
+             "blocks_at_cap": int((nd[:nblocks].cpu().numpy() >= 2 * cap).sum()),
+             **errors(back)}
+        if minexp != zfpx.MINEXP_NONE:
+            r["max_abs_error_vs_input"] = float(f"{np.abs(back - f32.reshape(-1)).max():.3e}")
+        out[name] = r
+        del sets
     return out
 
 
