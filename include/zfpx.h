@@ -200,8 +200,12 @@ int zfpx_decode_unpack_chunks(const zfpx_plan* plan, int32_t first, int32_t coun
  * asynchronous.  Both streams must be distinct; calls only enqueue (no
  * synchronisation): the send's bytes are in h_link once copy_stream reaches
  * the call's end, the recv's floats once compute_stream does.
- * zfpx_pipeline_create creates 2*groups HIP events (call it outside hot
- * loops); a pipeline refers to its plan, which must outlive it.
+ * A send waits (on the device) for the previous send's copies before it
+ * rewrites d_send, and a recv for the previous recv's decodes before it
+ * rewrites d_recv, so calls may follow each other without host
+ * synchronisation.  zfpx_pipeline_create creates 2*groups + 2 HIP events
+ * (call it outside hot loops); a pipeline refers to its plan, which must
+ * outlive it.
  * Errors: EINVAL (null pointers, bad rate or groups < 1), ENOSPC (a buffer
  * smaller than the coded size), the errors of the range calls.
  */

@@ -381,6 +381,9 @@ struct zfpx_pipeline {
   int rate = 0;
   std::vector<int32_t> first;          // group g = chunks [first[g], first[g + 1])
   std::vector<hipEvent_t> sent, recvd;  // per group
+  // end of the last send's copies / the last recv's decodes: the next call
+  // of the same kind waits for them before it overwrites the buffers
+  hipEvent_t send_done = nullptr, recv_done = nullptr;
 };
 
 int zfpx_pipeline_destroy(zfpx_pipeline* pp) {
@@ -389,6 +392,8 @@ int zfpx_pipeline_destroy(zfpx_pipeline* pp) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : pp->recvd)
     if (e) (void)hipEventDestroy(e);
+  if (pp->send_done) (void)hipEventDestroy(pp->send_done);
+  if (pp->recv_done) (void)hipEventDestroy(pp->recv_done);
   delete pp;
   return ZFPX_OK;
 }
@@ -405,6 +410,11 @@ int zfpx_pipeline_create(const zfpx_plan* p, int rate, int32_t groups, zfpx_pipe
   for (int32_t i = 0; i <= g; i++) pp->first[i] = (int32_t)((int64_t)i * p->nchunks / g);
   pp->sent.assign(g, nullptr);
   pp->recvd.assign(g, nullptr);
+  if (hipEventCreateWithFlags(&pp->send_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pp->recv_done, hipEventDisableTiming) != hipSuccess) {
+    zfpx_pipeline_destroy(pp);
+    return ZFPX_EHIP;
+  }
   for (int32_t i = 0; i < g; i++) {
     if (hipEventCreateWithFlags(&pp->sent[i], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&pp->recvd[i], hipEventDisableTiming) != hipSuccess) {
@@ -431,6 +441,8 @@ int zfpx_pipeline_send(zfpx_pipeline* pp, const float* d_src, int64_t src_elems,
   const size_t total = (size_t)pp->plan->nblocks * 8 * pp->rate;
   if (send_bytes < total || link_bytes < total) return ZFPX_ENOSPC;
   hipStream_t cs = (hipStream_t)compute_stream, xs = (hipStream_t)copy_stream;
+  // d_send is rewritten below: the previous send's copies must be done
+  if (hipStreamWaitEvent(cs, pp->send_done, 0) != hipSuccess) return ZFPX_EHIP;
   for (size_t i = 0; i + 1 < pp->first.size(); i++) {
     const int32_t c0 = pp->first[i], n = pp->first[i + 1] - c0;
     int st = zfpx_pack_encode_chunks(pp->plan, c0, n, d_src, src_elems, pp->rate, d_send,
@@ -445,7 +457,7 @@ int zfpx_pipeline_send(zfpx_pipeline* pp, const float* d_src, int64_t src_elems,
                        hipMemcpyDeviceToHost, xs) != hipSuccess)
       return ZFPX_EHIP;
   }
-  return ZFPX_OK;
+  return hipEventRecord(pp->send_done, xs) == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
 }
 
 int zfpx_pipeline_recv(zfpx_pipeline* pp, const void* h_link, size_t link_bytes, void* d_recv,
@@ -455,6 +467,8 @@ int zfpx_pipeline_recv(zfpx_pipeline* pp, const void* h_link, size_t link_bytes,
   const size_t total = (size_t)pp->plan->nblocks * 8 * pp->rate;
   if (recv_bytes < total || link_bytes < total) return ZFPX_ENOSPC;
   hipStream_t cs = (hipStream_t)compute_stream, xs = (hipStream_t)copy_stream;
+  // d_recv is rewritten below: the previous recv's decodes must be done
+  if (hipStreamWaitEvent(xs, pp->recv_done, 0) != hipSuccess) return ZFPX_EHIP;
   for (size_t i = 0; i + 1 < pp->first.size(); i++) {
     const int32_t c0 = pp->first[i], n = pp->first[i + 1] - c0;
     size_t off, bytes;
@@ -469,7 +483,7 @@ int zfpx_pipeline_recv(zfpx_pipeline* pp, const void* h_link, size_t link_bytes,
                                        dst_elems, cs);
     if (st) return st;
   }
-  return ZFPX_OK;
+  return hipEventRecord(pp->recv_done, cs) == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
 }
 
 // ---------------------------------------------------------------------------
