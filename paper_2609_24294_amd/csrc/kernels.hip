@@ -507,30 +507,51 @@ __global__ __launch_bounds__(256) void k_encode_var(Geo geo, const float* __rest
   }
 }
 
-// Tile offsets: exclusive prefix sums of the tile counts, and the total.
+// Tile offsets: exclusive prefix sums of the tile counts, and the total.  One
+// workgroup walks the counts in chunks of 8192: a coalesced load into LDS,
+// each thread sums 8 consecutive counts, a workgroup scan of the thread sums
+// (wavefront scans, then the 16 wavefront totals), and 8 offsets per thread.
 __global__ __launch_bounds__(1024) void k_var_scan(const uint32_t* __restrict__ tile_count,
                                                    int32_t ntiles, int64_t* __restrict__ tile_off) {
-  __shared__ int64_t part[1024];
-  const int i = threadIdx.x;
-  const int32_t per = (ntiles + 1023) / 1024;
-  const int32_t k0 = i * per < ntiles ? i * per : ntiles;
-  const int32_t k1 = k0 + per < ntiles ? k0 + per : ntiles;
-  int64_t sum = 0;
-  for (int32_t k = k0; k < k1; k++) sum += tile_count[k];
-  part[i] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int64_t y = i >= o ? part[i - o] : 0;
+  constexpr int kPer = 8, kChunk = 1024 * kPer;
+  __shared__ uint32_t buf[kChunk];
+  __shared__ uint32_t wtot[16];
+  const int i = threadIdx.x, lane = i & 63, w = i >> 6;
+  int64_t carry = 0;
+  for (int32_t base = 0; base < ntiles; base += kChunk) {
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const int32_t k = base + j * 1024 + i;
+      buf[j * 1024 + i] = k < ntiles ? tile_count[k] : 0u;
+    }
     __syncthreads();
-    part[i] += y;
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      v[j] = buf[i * kPer + j];
+      sum += v[j];
+    }
+    const uint32_t incl = wave_incl_scan(sum, lane);
+    if (lane == 63) wtot[w] = incl;
     __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+      const uint32_t t = wtot[k];
+      before += k < w ? t : 0u;
+      total += t;
+    }
+    int64_t run = carry + before + (incl - sum);
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const int32_t k = base + i * kPer + j;
+      if (k < ntiles) tile_off[k] = run;
+      run += v[j];
+    }
+    carry += total;
+    __syncthreads();  // buf and wtot are rewritten by the next chunk
   }
-  int64_t run = part[i] - sum;
-  for (int32_t k = k0; k < k1; k++) {
-    tile_off[k] = run;
-    run += tile_count[k];
-  }
-  if (i == 1023) tile_off[ntiles] = part[1023];
+  if (i == 0) tile_off[ntiles] = carry;
 }
 
 // Copy each tile's words from its staging slot to its offset; words at or
