@@ -1,6 +1,8 @@
 /*
- * zfpx.h -- fixed-rate ZFP coding of spectral-transform transpose buffers on
- * AMD Instinct MI355X (gfx950).
+ * zfpx.h -- ZFP coding of spectral-transform transpose buffers on AMD
+ * Instinct MI355X (gfx950): fixed rate (the paper's mode), the variable-size
+ * precision and accuracy modes, the float16 comparator, batching, a serving
+ * loop and a chunk-wise pipeline over a link.
  *
  * The paper this implements (Breschi & Vella, "Toward GPU-Resident Climate
  * Models: a feasibility study on lossy compression for the spherical harmonic
