@@ -193,3 +193,45 @@ def test_zlambda_share_full_size_sampled(zfpx_lib):
             assert np.array_equal(gw[off[b]:off[b] + k], ow[j].view(np.uint32)[:k]), b
             v = oracle.decode_block_var(ow[j], maxprec, minexp, cap)
             assert np.array_equal(f32bits(host_out[pos[j][ins[j]]]), f32bits(v[ins[j]])), b
+
+
+def test_encode_decode_captured_in_a_graph(zfpx_lib):
+    # the variable-size calls only enqueue kernels (no memset, no allocation):
+    # captured once, each replay on new input matches the eager calls
+    Z = zfpx_lib
+    cs = W.zlambda_chunkset(nfields=1, nlev=21, nrows=16, npts=501, nchunks=4)
+    plan = Z.Plan.from_chunkset(cs)
+    rng = np.random.default_rng(316)
+    maxprec, minexp, cap = 32, oracle.accuracy_minexp(1e-3), 16
+    src = torch.empty(cs.buffer_elems, dtype=torch.float32, device=DEV)
+    out = torch.empty_like(src)
+    mw, nt, wb = Z.zfpx_plan_var_sizes(plan, cap)
+    words = torch.empty(mw, dtype=torch.int32, device=DEV)
+    nd = torch.empty(plan.nblocks, dtype=torch.uint8, device=DEV)
+    toff = torch.empty(nt + 1, dtype=torch.int64, device=DEV)
+    work = torch.empty((wb + 7) // 8, dtype=torch.int64, device=DEV)
+    src.copy_(torch.from_numpy(np.cumsum(rng.standard_normal(cs.buffer_elems)).astype(np.float32)))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            Z.zfpx_plan_encode_var(plan, src, maxprec, minexp, cap, words, nd, toff, work)
+            Z.zfpx_plan_decode_var(plan, words, nd, toff, maxprec, minexp, cap, out)
+    for rep in range(3):
+        host = np.cumsum(rng.standard_normal(cs.buffer_elems)).astype(np.float32)
+        src.copy_(torch.from_numpy(host))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got_words = words[:int(toff[-1].item())].clone()
+        got_out = out.clone()
+        ew, end_, eto = Z.zfpx_plan_encode_var(plan, src, maxprec, minexp, cap)
+        eo = torch.empty_like(src)
+        Z.zfpx_plan_decode_var(plan, ew, end_, eto, maxprec, minexp, cap, eo)
+        torch.cuda.synchronize()
+        assert torch.equal(toff, eto) and torch.equal(nd, end_[:plan.nblocks])
+        assert torch.equal(got_words, ew[:int(eto[-1].item())]), rep
+        assert torch.equal(got_out.view(torch.int32), eo.view(torch.int32)), rep
+        ow, ond, otoff = oracle.pack_encode_var(cs, host, maxprec, minexp, cap)
+        assert np.array_equal(got_words.cpu().numpy().view(np.uint32), ow), rep
