@@ -22,6 +22,7 @@ import dataclasses
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -90,9 +91,10 @@ def parse():
     return ap.parse_args()
 
 
-def timed_loop(fn_list, steps, warmup, torch):
+def timed_loop(fn_list, steps, warmup, torch, detail=False):
     """Run warmup + steps iterations of a list of launch callables on the
-    current stream; per callable, the mean event-timed duration (ms)."""
+    current stream; per callable, the mean event-timed duration (ms) (and,
+    with detail, the per-step durations)."""
     s = torch.cuda.current_stream()
     for i in range(warmup):
         for f in fn_list:
@@ -109,8 +111,11 @@ def timed_loop(fn_list, steps, warmup, torch):
             e[j + 1].record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = [sum(evs[i][j].elapsed_time(evs[i][j + 1]) for i in range(steps)) / steps
-           for j in range(len(fn_list))]
+    each = [[evs[i][j].elapsed_time(evs[i][j + 1]) for i in range(steps)]
+            for j in range(len(fn_list))]
+    per = [sum(e) / steps for e in each]
+    if detail:
+        return wall, per, each
     return wall, per
 
 
@@ -150,7 +155,11 @@ def main():
         return lambda i: zfpx.zfpx_decode_unpack(plan, send[r][i % nsets], r, dst[i % nsets])
 
     log(f"timing rate {rate}: {args.warmup} warmup + {args.steps} steps")
-    wall, (t_enc, t_dec) = timed_loop([enc(rate), dec(rate)], args.steps, args.warmup, torch)
+    wall, (t_enc, t_dec), each = timed_loop([enc(rate), dec(rate)], args.steps, args.warmup,
+                                            torch, detail=True)
+    spread = {f"{name}_ms_{stat}": round(float(f(each[j])), 4)
+              for j, name in enumerate(("encode", "decode"))
+              for stat, f in (("median", statistics.median), ("min", min))}
     ms_per_step = 1000.0 * wall / args.steps
     value = in_bytes * args.steps / wall / 1e9
 
@@ -265,6 +274,7 @@ def main():
                    "buffer_sets": nsets},
         "encode_ms": round(t_enc, 4),
         "decode_ms": round(t_dec, 4),
+        **spread,
         "encode_hbm_frac": round(enc_gbs / HBM_PEAK_GBS, 4),
         "decode_hbm_frac": round(dec_gbs / HBM_PEAK_GBS, 4),
         "bytes_reduction": round(in_bytes / coded, 3),
@@ -757,11 +767,29 @@ def cpu_baseline(cs, rate):
         times.append((t1 - t0, t2 - t1))
     te, td = min(times, key=lambda t: t[0] + t[1])
     nvals = cs.values()
+    # one thread, same work
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    words = oracle.pack_encode(cs, x32, rate)
+    t1 = time.perf_counter()
+    oracle.decode_unpack(cs, words, rate, back)
+    t2 = time.perf_counter()
+    oracle.set_threads(cores)
+    # numpy's float16 cast and back (the comparator on the host)
+    t3 = time.perf_counter()
+    h = x32.astype(np.float16)
+    t4 = time.perf_counter()
+    _ = h.astype(np.float32)
+    t5 = time.perf_counter()
     return {"value": round(4 * nvals / (te + td) / 1e9, 4), "unit": "GB/s", "cores": cores,
             "kind": "oracle",
             "sample": f"whole z->lambda share ({nvals} values), pack+encode then decode+unpack "
                       f"at rate {rate}, best of 2",
-            "encode_s": round(te, 3), "decode_s": round(td, 3)}
+            "encode_s": round(te, 3), "decode_s": round(td, 3),
+            "one_thread": {"encode_s": round(t1 - t0, 3), "decode_s": round(t2 - t1, 3),
+                           "gbs": round(4 * nvals / (t2 - t0) / 1e9, 4)},
+            "numpy_f16": {"truncate_s": round(t4 - t3, 3), "restore_s": round(t5 - t4, 3),
+                          "gbs": round(4 * nvals / (t5 - t3) / 1e9, 4)}}
 
 
 if __name__ == "__main__":

@@ -83,6 +83,7 @@ _SIGS = {
     "orc_decode_block_var": (None, [_U64P, _INT, _INT, _I64, _F32P]),
     "orc_pack_encode_var": (None, _CHUNK_ARGS + [_F32P, _INT, _INT, _INT, _U32P, _U8P, _I64P]),
     "orc_decode_unpack_var": (None, _CHUNK_ARGS + [_U32P, _U8P, _INT, _INT, _INT, _F32P]),
+    "orc_set_threads": (None, [_INT]),
     "orc_pack_encode_var_sample": (None, _CHUNK_ARGS + [_F32P, _INT, _INT, _INT, _I64P, _I64,
                                                         _U64P, _I64P, _I64P, _I32P]),
 }
@@ -106,6 +107,11 @@ def lib():
 # ---------------------------------------------------------------------------
 # Stage-level access (for the invariant tests)
 # ---------------------------------------------------------------------------
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the C oracle's loops."""
+    lib().orc_set_threads(int(n))
+
 
 def block_exponent(v):
     v = np.ascontiguousarray(v, dtype=np.float32)

@@ -46,6 +46,7 @@
  * that no C signed-overflow rule is involved.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -795,3 +796,7 @@ void orc_pack_encode_var_sample(int nchunks, const int64_t *chunk_base,
   }
   free(first);
 }
+
+/* Threads used by the OpenMP loops above (for timing the oracle). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
