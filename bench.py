@@ -87,6 +87,8 @@ def parse():
                     help="skip the chunk-pipelined send/receive over a host link")
     ap.add_argument("--no-fourier", action="store_true",
                     help="skip the Fourier-space lambda->theta buffer leg")
+    ap.add_argument("--no-sensitivity", action="store_true",
+                    help="skip the data-roughness leg (T255 and white noise)")
     ap.add_argument("--serving-requests", type=int, default=10000)
     return ap.parse_args()
 
@@ -230,6 +232,12 @@ def main():
     if not args.no_accuracy:
         accuracy = accuracy_report(plan, src[0], dst[0], nvals, nblocks, torch, zfpx, W)
 
+    # last user of the share's buffers: it overwrites them with other data
+    sensitivity = None
+    if not args.no_sensitivity:
+        sensitivity = sensitivity_report(plan, src, dst, nblocks, max(5, args.steps // 2),
+                                         torch, zfpx, W)
+
     large = None
     if not args.no_large:
         del src, dst, send
@@ -294,6 +302,7 @@ def main():
         **extras,
         "accuracy": accuracy,
         "variable": variable,
+        "sensitivity": sensitivity,
         "pipeline": pipeline,
         "fourier": fourier,
         "large": large,
@@ -359,6 +368,40 @@ def variable_report(plan, src, dst, nvals, nblocks, steps, torch, zfpx, W):
             r["tolerance"] = 1e-2
         out[name] = r
         del sets
+    return out
+
+
+def sensitivity_report(plan, src, dst, nblocks, steps, torch, zfpx, W):
+    """How the codec's speed depends on the data: the same share and launch at
+    rates 16 and 8 with the fields synthesised at T255 instead of T42, and
+    with white noise (every coefficient significant from the first planes:
+    the coder's worst case).  The headline buffers are overwritten."""
+    import numpy as np
+
+    log("sensitivity: the share at T255 and as white noise")
+    nsets = len(src)
+    nvals = src[0].numel()
+    out = {}
+    x255, _ = W.zlambda_fields(L=255, want_f64=False)
+    rng = np.random.Generator(np.random.PCG64(W.SEED_BASE + 7))
+    noise = rng.standard_normal(nvals, dtype=np.float32)
+    for name, host in (("T255", x255.reshape(-1)), ("white_noise", noise)):
+        for i in range(nsets):
+            src[i].copy_(torch.from_numpy(host))
+        r = {}
+        for rate in (16, 8):
+            send = [torch.empty(nblocks * rate, dtype=torch.int64, device=src[0].device)
+                    for _ in range(nsets)]
+            enc = lambda i: zfpx.zfpx_pack_encode(plan, src[i % nsets], rate, send[i % nsets])
+            dec = lambda i: zfpx.zfpx_decode_unpack(plan, send[i % nsets], rate, dst[i % nsets])
+            _, (te, td) = timed_loop([enc, dec], steps, 2, torch)
+            alg = 4 * nvals + nblocks * 8 * rate
+            r[f"rate{rate}"] = {"encode_ms": round(te, 4), "decode_ms": round(td, 4),
+                                "encode_hbm_frac": round(alg / (te * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "decode_hbm_frac": round(alg / (td * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            del send
+        out[name] = r
+    torch.cuda.synchronize()
     return out
 
 
