@@ -235,3 +235,37 @@ def test_encode_decode_captured_in_a_graph(zfpx_lib):
         assert torch.equal(got_out.view(torch.int32), eo.view(torch.int32)), rep
         ow, ond, otoff = oracle.pack_encode_var(cs, host, maxprec, minexp, cap)
         assert np.array_equal(got_words.cpu().numpy().view(np.uint32), ow), rep
+
+
+def test_large_buffer_full_size_sampled(zfpx_lib):
+    # O2560 x 90 levels (9.47 GB, 37,859,840 blocks) in one launch: offsets are
+    # the exclusive scan of the counts over 591,560 tiles, and sampled blocks
+    # match the oracle (stream words and decoded floats)
+    Z = zfpx_lib
+    cs = W.large_chunkset()
+    x32 = W.large_field_repeated(W.large_field_levels(8))
+    plan = Z.Plan.from_chunkset(cs)
+    d = torch.from_numpy(x32.reshape(-1)).to(DEV)
+    maxprec, minexp, cap = 16, NONE, 16
+    words, nd, toff = Z.zfpx_plan_encode_var(plan, d, maxprec, minexp, cap)
+    out = torch.empty_like(d)
+    Z.zfpx_plan_decode_var(plan, words, nd, toff, maxprec, minexp, cap, out)
+    torch.cuda.synchronize()
+    gnd = nd.cpu().numpy()
+    gtoff = toff.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum(gnd.astype(np.int64))])
+    assert gtoff.size == 591560 + 1
+    assert np.array_equal(gtoff, np.concatenate([off[:-1][::64], off[-1:]]))
+    rng = np.random.default_rng(317)
+    ids = np.unique(np.concatenate([rng.choice(plan.nblocks, 1500, replace=False),
+                                    [0, 63, 64, plan.nblocks - 1]]))
+    ow, ol, pos, ins = oracle.pack_encode_var_sample(cs, x32, maxprec, minexp, cap, ids)
+    assert np.array_equal(gnd[ids], (ol + 31) // 32)
+    flat = out.view(-1)
+    for j, b in enumerate(ids):
+        k = int(gnd[b])
+        got = words[int(off[b]):int(off[b]) + k].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, ow[j].view(np.uint32)[:k]), b
+        v = oracle.decode_block_var(ow[j], maxprec, minexp, cap)
+        p = torch.from_numpy(pos[j][ins[j]]).to(DEV)
+        assert np.array_equal(flat[p].cpu().numpy().view(np.uint32), v[ins[j]].view(np.uint32)), b
