@@ -647,6 +647,21 @@ def large_report(torch, zfpx, W, reps=5):
             "decode_hbm_frac": round(alg / (td * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "algorithmic_bytes": alg}
         del send
+    # precision mode 16 (cap 16): three encode launches, one decode launch
+    log("large: precision 16 (variable size)")
+    w, nd, to = zfpx.zfpx_plan_encode_var(plan, src, 16, zfpx.MINEXP_NONE, 16)
+    enc = lambda i: zfpx.zfpx_plan_encode_var(plan, src, 16, zfpx.MINEXP_NONE, 16, w, nd, to)
+    dec = lambda i: zfpx.zfpx_plan_decode_var(plan, w, nd, to, 16, zfpx.MINEXP_NONE, 16, dst)
+    _, (te, td) = timed_loop([enc, dec], reps, 1, torch)
+    torch.cuda.synchronize()
+    coded = 4 * int(to[-1].item()) + plan.nblocks + 8 * to.numel()
+    out["precision16"] = {"encode_ms": round(te, 3), "decode_ms": round(td, 3),
+                          "bits_per_value": round(8 * coded / plan.nvalues, 3),
+                          "encode_hbm_frac": round((in_bytes + coded) / (te * 1e-3) / 1e9
+                                                   / HBM_PEAK_GBS, 4),
+                          "decode_hbm_frac": round((in_bytes + coded) / (td * 1e-3) / 1e9
+                                                   / HBM_PEAK_GBS, 4)}
+    del w, nd, to
     del src, dst
     torch.cuda.empty_cache()
     return out
