@@ -441,8 +441,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // writes the tile's words, compacted, to its own staging slot of 64 * 2 * cap
 // words, plus the per-block counts and the tile's count; (2) one workgroup
 // scans the tile counts into tile offsets; (3) each wavefront copies its
-// tile's words from the staging slot to the tile's offset.  Every store of
-// the three is a contiguous 256-byte stretch per wavefront instruction.
+// tile's words from the staging slot to the tile's offset.  The words, which
+// are the bulk of the traffic, are stored as contiguous 256-byte stretches
+// per wavefront instruction in both (1) and (3).
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
 #pragma unroll
