@@ -284,6 +284,30 @@ ZFPX_HD uint64_t window64(const uint64_t* s, uint32_t pos) {
   return (uint64_t)funnel32(d1, d0, pos) | ((uint64_t)funnel32(d2, d1, pos) << 32);
 }
 
+// The three 32-bit words that hold the window at pos, and the window itself.
+struct Words3 {
+  uint32_t w0, w1, w2;
+};
+ZFPX_HD Words3 window_words(const uint64_t* s, uint32_t pos) {
+  const u32_alias* d = reinterpret_cast<const u32_alias*>(s) + (pos >> 5);
+  return Words3{d[0], d[1], d[2]};
+}
+ZFPX_HD uint64_t window_of(const Words3& w, uint32_t pos) {
+  return (uint64_t)funnel32(w.w1, w.w0, pos) | ((uint64_t)funnel32(w.w2, w.w1, pos) << 32);
+}
+
+// Make the words of two windows available at this point (an empty asm that
+// reads and writes all six): the six reads are issued first and waited for
+// together, one LDS round trip for both windows.
+ZFPX_HD void pin_words(Words3& a, Words3& b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(a.w0), "+v"(a.w1), "+v"(a.w2), "+v"(b.w0), "+v"(b.w1), "+v"(b.w2));
+#else
+  (void)a;
+  (void)b;
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Encoder
 // ---------------------------------------------------------------------------
@@ -401,7 +425,15 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
     uint64_t x = 0;
     if (pos < maxbits && k >= kmin) {
       int m = (int)(maxbits - pos) < n ? (int)(maxbits - pos) : n;
-      x = window64(in, pos) & low_mask(m);  // the first n bits verbatim
+      // Both windows of the plane in one round trip: the verbatim bits at
+      // pos and the group tests after them (pos + m <= maxbits, so both stay
+      // inside the slice).  Left to itself the compiler waits for the first
+      // window before reading the second, and moves part of the second
+      // behind a branch: three dependent round trips per plane.
+      Words3 wv = window_words(in, pos), ws = window_words(in, pos + m);
+      pin_words(wv, ws);
+      uint64_t s = window_of(ws, pos + m);  // group tests and scans
+      x = window_of(wv, pos) & low_mask(m);  // the first n bits verbatim
       pos += m;
       if (n < 64 && pos < maxbits) {
         // Common case first: every group test and scan of the plane lies in
@@ -409,7 +441,6 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
         // coefficient 63 (whose one would be implied).  Otherwise the plane
         // is decoded group by group from the same state.
         bool done = false;
-        uint64_t s = window64(in, pos);
         uint64_t y = 0;
         int c = 0, used = 1;  // coefficients and bits taken; the closing zero
         while (s & 1) {
