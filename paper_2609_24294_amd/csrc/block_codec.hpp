@@ -307,6 +307,13 @@ ZFPX_HD void pin_words(Words3& a, Words3& b) {
   (void)b;
 #endif
 }
+ZFPX_HD void pin_words(Words3& a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(a.w0), "+v"(a.w1), "+v"(a.w2));
+#else
+  (void)a;
+#endif
+}
 
 // ---------------------------------------------------------------------------
 // Encoder
@@ -410,7 +417,11 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
                           int minexp = kMinExpNone) {
   const int rate = RATE > 0 ? RATE : rate_rt;
   const uint32_t maxbits = 64u * (uint32_t)rate;
-  uint64_t head = in[0];
+  // The header (bits 0..8) and, in the same three words, both windows of
+  // the first plane (n = 0, so they start at bit 9): one round trip.
+  Words3 wfirst = window_words(in, 0);
+  pin_words(wfirst);
+  const uint32_t head = wfirst.w0;
   uint32_t pos = maxbits;  // an empty block decodes to zeros
   int emax = 0, kmin = 0;
   if (head & 1) {
@@ -430,8 +441,12 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
       // inside the slice).  Left to itself the compiler waits for the first
       // window before reading the second, and moves part of the second
       // behind a branch: three dependent round trips per plane.
-      Words3 wv = window_words(in, pos), ws = window_words(in, pos + m);
-      pin_words(wv, ws);
+      Words3 wv = wfirst, ws = wfirst;
+      if (k < 31) {
+        wv = window_words(in, pos);
+        ws = window_words(in, pos + m);
+        pin_words(wv, ws);
+      }
       uint64_t s = window_of(ws, pos + m);  // group tests and scans
       x = window_of(wv, pos) & low_mask(m);  // the first n bits verbatim
       pos += m;

@@ -292,6 +292,24 @@ __device__ __forceinline__ void copy_tile(uint64_t* __restrict__ g, uint64_t* ld
     constexpr int step = 64 / RATE;  // blocks per row of 64 words
     const int b = lane / RATE, idx = lane % RATE;
     uint64_t* l = lds + b * stride + idx;
+    if (nact == 64) {
+      // A whole tile (nact is wave-uniform): every read is issued before any
+      // is waited for, one round trip in all (behind per-word guards the
+      // compiler waits for each word before the next).
+      uint64_t v[RATE];
+      if (TO_GLOBAL) {
+#pragma unroll
+        for (int j = 0; j < RATE; j++) v[j] = l[j * step * stride];
+#pragma unroll
+        for (int j = 0; j < RATE; j++) gstore64<COH>(g + lane + 64 * j, v[j]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < RATE; j++) v[j] = gload64<COH>(g + lane + 64 * j);
+#pragma unroll
+        for (int j = 0; j < RATE; j++) l[j * step * stride] = v[j];
+      }
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < RATE; j++) {
       if (b + j * step < nact) {
