@@ -267,6 +267,20 @@ __device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView
   }
 }
 
+// Make loaded values available at this point (an empty asm that reads and
+// writes them): the loads are then all issued before the first wait, instead
+// of one round trip each behind the guards of their uses.
+__device__ __forceinline__ void pin_words64(uint64_t (&v)[4]) {
+  asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));
+}
+__device__ __forceinline__ void pin_words32(uint32_t (&v)[4]) {
+  asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));
+}
+__device__ __forceinline__ void pin_words32(uint32_t (&v)[8]) {
+  asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]),
+               "+v"(v[6]), "+v"(v[7]));
+}
+
 // Copy a tile's coded words between LDS slices (stride words per block) and
 // global memory (rate words per block, contiguous).  For rates dividing 64,
 // lane l always handles word l % rate of every (64/rate)-th block, so the
@@ -323,13 +337,29 @@ __device__ __forceinline__ void copy_tile(uint64_t* __restrict__ g, uint64_t* ld
     const int rate = RATE > 0 ? RATE : rate_rt;
     const int stride = (rate + kSlackWords) | 1;
     const int nw = nact * rate;
-    for (int w = lane; w < nw; w += 64) {
-      int blk = w / rate;
-      int idx = w - blk * rate;
-      if (TO_GLOBAL)
-        gstore64<COH>(g + w, lds[blk * stride + idx]);
-      else
-        lds[blk * stride + idx] = gload64<COH>(g + w);
+    // four words per lane per round, all read before any is waited for
+    // (reads past the end repeat word 0 and are not stored)
+    for (int w0 = lane; w0 < nw; w0 += 256) {
+      uint64_t v[4];
+      int at[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int w = w0 + 64 * j < nw ? w0 + 64 * j : 0;
+        const int blk = w / rate;
+        at[j] = blk * stride + (w - blk * rate);
+        v[j] = TO_GLOBAL ? lds[at[j]] : gload64<COH>(g + w);
+      }
+      pin_words64(v);
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int w = w0 + 64 * j;
+        if (w < nw) {
+          if (TO_GLOBAL)
+            gstore64<COH>(g + w, v[j]);
+          else
+            lds[at[j]] = v[j];
+        }
+      }
     }
   }
 }
@@ -588,9 +618,18 @@ __global__ __launch_bounds__(256) void k_var_place(const uint32_t* __restrict__ 
   const uint32_t count = uniform_load(tile_count, t);
   const uint64_t o = (uint64_t)uniform_load(tile_off, t);
   const uint32_t* in = stage + (size_t)t * 64 * 2 * cap;
-#pragma unroll 4
-  for (uint32_t q = lane; q < count; q += 64)
-    if (o + q < out_words) out[o + q] = in[q];
+  for (uint32_t q0 = lane; q0 < count; q0 += 256) {
+    // four words per lane read at once (past the count: word 0, not stored)
+    uint32_t r[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) r[j] = in[q0 + 64 * j < count ? q0 + 64 * j : 0];
+    pin_words32(r);
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const uint32_t q = q0 + 64 * j;
+      if (q < count && o + q < out_words) out[o + q] = r[j];
+    }
+  }
 }
 
 // Any content of the stream, counts and offsets decodes without a fault:
@@ -618,16 +657,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const uint64_t o = (uint64_t)uniform_load(tile_off, t) + (incl - nd);
   for (int i = 0; i < stride; i++) slice[i] = 0;
   uint32_t* s32 = reinterpret_cast<uint32_t*>(slice);
+  if (in_words == 0) nd = 0;  // nothing to read: every block decodes from zeros
   for (uint32_t i0 = 0; i0 < nd; i0 += 8) {
+    // eight words read at once (words outside the stream are read at 0 and
+    // replaced by zero), then written to the slice
     uint32_t r[8];
+    bool ok[8];
 #pragma unroll
     for (int j = 0; j < 8; j++) {
       const uint64_t w = o + i0 + j;
-      r[j] = (i0 + j < nd && w < in_words && w >= o) ? in[w] : 0u;
+      ok[j] = i0 + j < nd && w < in_words && w >= o;
+      r[j] = in[ok[j] ? w : 0];
     }
+    pin_words32(r);
 #pragma unroll
     for (int j = 0; j < 8; j++)
-      if (i0 + j < nd) s32[i0 + j] = r[j];
+      if (i0 + j < nd) s32[i0 + j] = ok[j] ? r[j] : 0u;
   }
   wave_sync_lds();
   if (lane < nact) {
