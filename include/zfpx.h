@@ -12,8 +12,8 @@
  * computation, with no host-device copies (Section I).  It uses ZFP in
  * fixed-rate mode: 4x4x4 blocks coded independently into exactly r bits per
  * value, so every message has a size known in advance (Sections II-C and
- * III-B), and compares with casting the buffer to float16 and back (Sections I
- * and III-F).
+ * IV-B), and compares with casting the buffer to float16 and back (Sections I
+ * and IV-F).
  *
  * Conventions common to every entry point
  *  - Device buffers are caller-owned device memory (hipMalloc or a PyTorch
@@ -173,7 +173,7 @@ int zfpx_decode_unpack(const zfpx_plan* plan, const void* d_recv, size_t recv_by
  * streams are read/written at their offsets inside the whole send buffer, so
  * d_send/d_recv still point at the start of the buffer.  This is the
  * one-launch-per-chunk form, and the unit for overlapping coding with
- * sending chunk by chunk (paper Section III-D: the serial model could be
+ * sending chunk by chunk (paper Section IV-D: the serial model could be
  * pipelined).
  */
 int zfpx_pack_encode_chunks(const zfpx_plan* plan, int32_t first, int32_t count,
@@ -190,7 +190,7 @@ int zfpx_decode_unpack_chunks(const zfpx_plan* plan, int32_t first, int32_t coun
 /*
  * The paper adds codec time before and after the exchange (t_compress +
  * t_comm + t_decompress) and notes that compressing and sending could be
- * pipelined (Section III-D).  A pipeline cuts the plan's chunks into `groups`
+ * pipelined (Section IV-D).  A pipeline cuts the plan's chunks into `groups`
  * consecutive groups (fewer if there are fewer chunks):
  *   send: group g is encoded on compute_stream, then copied device -> host
  *         (h_link, at the group's offset in the fixed-rate stream) on
@@ -229,7 +229,7 @@ int zfpx_pipeline_destroy(zfpx_pipeline* pipe);
 /*
  * ZFP's precision and accuracy modes, which the paper sets aside for future
  * work because their messages do not have a size known in advance (Sections
- * II-C and III-B).  They run the fixed-rate block coder but stop after the
+ * II-C and IV-B).  They run the fixed-rate block coder but stop after the
  * bit planes 31 .. 32-p of a block with exponent emax, where
  *   p = min(maxprec, max(0, emax - minexp + 8))      (8 = 2 (d+1), d = 3);
  * p = 0 codes the block as the single bit 0.
@@ -426,7 +426,7 @@ int zfpx_plain_replay(const zfpx_request* rq, const double* arrival_s, int64_t n
  * ties to even (subnormals kept, overflow to infinity, NaN stays NaN).
  * f16_restore: exact widening back to float32.  The paper's comparator casts
  * the buffer to float16 before sending and back on receipt (Sections I and
- * III-F).  n may be 0; pointers must be 4-byte (in) / 2-byte (out) aligned.
+ * IV-F).  n may be 0; pointers must be 4-byte (in) / 2-byte (out) aligned.
  */
 int f16_truncate(const float* d_in, size_t n, uint16_t* d_out, void* stream);
 int f16_restore(const uint16_t* d_in, size_t n, float* d_out, void* stream);

@@ -8,7 +8,7 @@ The codec itself is plain C (``zfp_oracle.c``), compiled with gcc into
 ``liboracle.so``; this module only marshals numpy arrays through ctypes.  The
 float16 comparator is numpy's own IEEE binary16 conversion (round to nearest,
 ties to even, subnormals kept, overflow to infinity), which is the definition
-the paper's comparator uses (Section III-F: cast to float16 and back).
+the paper's comparator uses (Section IV-F: cast to float16 and back).
 
 Parity unpinned: byte compatibility with the ZFP library (not available), and
 the paper's error figures (its input data are not available).

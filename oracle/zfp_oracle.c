@@ -8,7 +8,7 @@
  * header, table or helper with the HIP library.
  *
  * What is computed, and where it comes from:
- *  - The paper (Section II-C, "ZFP Fixed-Rate Compression"; Section III-B,
+ *  - The paper (Section II-C, "ZFP Fixed-Rate Compression"; Section IV-B,
  *    "Compression Configuration") fixes the method: ZFP in fixed-rate mode,
  *    arrays cut into independent 4x4x4 blocks, a lifting decorrelating
  *    transform, precision reduction, exactly r compressed bits per value,
@@ -33,7 +33,7 @@
  *                 middle of a scan the decoder still sets the bit at the
  *                 current scan position.
  *  - The variable-size modes (fixed precision, fixed accuracy) that the paper
- *    names as future work (Sections II-C and III-B) are the same coder
+ *    names as future work (Sections II-C and IV-B) are the same coder
  *    stopped after a block-dependent number of bit planes; see "Variable-size
  *    blocks" below for the rule and the stream layout used for them.
  *  - "Parity unpinned": byte compatibility with the ZFP library itself (no
@@ -373,7 +373,7 @@ void orc_decode_block(const uint64_t *words, int rate, float v[NVAL]) {
 /* Variable-size blocks: fixed-precision and fixed-accuracy modes             */
 /* ------------------------------------------------------------------------- */
 /*
- * The paper (Sections II-C and III-B) names ZFP's two variable-size modes as
+ * The paper (Sections II-C and IV-B) names ZFP's two variable-size modes as
  * the alternative to fixed rate that future work may take up: a fixed number
  * of bit planes (precision mode) and a fixed absolute error tolerance
  * (accuracy mode).  In ZFP's description both run the same block coder as

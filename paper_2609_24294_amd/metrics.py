@@ -1,8 +1,8 @@
 """Host-side accuracy and size reporting (not timed, not on the GPU path).
 
-Relative error as the paper defines it (Section III-F): eps = ||x - xhat|| /
+Relative error as the paper defines it (Section IV-F): eps = ||x - xhat|| /
 ||x|| with x the original and xhat the reconstructed values; the paper
-reports its distribution over all 4x4x4 blocks and the mean (Section IV-C).
+reports its distribution over all 4x4x4 blocks and the mean (Section V-C).
 Here the norm is the Euclidean one, taken per block over the block's real
 (unpadded) values; blocks with ||x|| = 0 are skipped.  The global error over
 the whole field and pointwise |x - xhat| / |x| statistics are reported too.

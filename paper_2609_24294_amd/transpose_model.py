@@ -1,6 +1,6 @@
 """Transposition-time model for the row all-to-all of the SHT.
 
-The paper (Section IV, network simulation and time model) adds the measured
+The paper (Section IV-D, network simulation and time model) adds the measured
 compression time before and the measured decompression time after the
 simulated all-to-all: t = t_compress + t_comm + t_decompress, a serial model
 it calls a conservative upper bound.  Its network is a simulated Dragonfly

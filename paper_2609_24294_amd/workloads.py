@@ -5,7 +5,7 @@ arithmetic, imports nothing else from this package, and serves both the
 HIP path and the CPU oracle in the tests.
 
 Stand-in for the paper's data.  The paper compresses DYAMOND fields (Section
-III-A: temperature and ozone on a 2560 x 1281 grid, float32) which are not
+IV-A: temperature and ozone on a 2560 x 1281 grid, float32) which are not
 available here.  Instead every field is a random spherical-harmonic series
 truncated at total wavenumber L (T42 by default) with coefficient variance
 proportional to (l+1)^-3, correlated 0.9 from one vertical level to the next,

@@ -1,4 +1,4 @@
-"""Error metric of the paper (Section III-F) on hand-checkable cases."""
+"""Error metric of the paper (Section IV-F) on hand-checkable cases."""
 import numpy as np
 
 from paper_2609_24294_amd import metrics

@@ -1,7 +1,7 @@
 """Pins of the oracle's variable-size modes (fixed precision, fixed accuracy).
 
 The paper names these ZFP modes as the variable-size alternative to fixed
-rate (Sections II-C and III-B).  The checks: the accuracy mode's absolute
+rate (Sections II-C and IV-B).  The checks: the accuracy mode's absolute
 error bound, the reduction to fixed rate at full precision, exactness of the
 kept bit planes, embedded prefixes across precisions, the tolerance-to-exponent
 rule on exact powers of two, agreement with the independent Python writing,
