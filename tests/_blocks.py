@@ -1,4 +1,5 @@
-"""Seeded families of 4x4x4 test blocks (inputs only)."""
+"""Seeded families of 4x4x4 test blocks, and the in-range value count of a
+chunk block from the chunk geometry (inputs and geometry only)."""
 import numpy as np
 
 
@@ -42,3 +43,29 @@ def blocks_to_array(blocks):
 def array_to_blocks(a):
     n = a.shape[2] // 4
     return np.ascontiguousarray(a.reshape(4, 4, n, 4).transpose(2, 0, 1, 3).reshape(n, 64))
+
+
+def real_values(cs, ids):
+    """In-range values of each listed block, from the chunk geometry alone:
+    blocks are numbered by chunk, then level block, then row group (rows in
+    fours), then x block; a group is as wide as its longest row."""
+    first, per_chunk = [0], []
+    for c in range(cs.nchunks):
+        r0, r1 = int(cs.row_start[c]), int(cs.row_start[c + 1])
+        lens = cs.row_len[r0:r1].astype(np.int64)
+        widths = [-(-int(lens[g:g + 4].max()) // 4) for g in range(0, lens.size, 4)]
+        per_lb = int(sum(widths))
+        per_chunk.append((lens, np.cumsum([0] + widths), per_lb, int(cs.levels[c])))
+        first.append(first[-1] + per_lb * -(-int(cs.levels[c]) // 4))
+    first = np.array(first)
+    out = np.zeros(len(ids), np.int64)
+    for j, b in enumerate(ids):
+        c = int(np.searchsorted(first, b, side="right") - 1)
+        lens, gstart, per_lb, nlev = per_chunk[c]
+        rem = int(b - first[c])
+        bz, rem = divmod(rem, per_lb)
+        g = int(np.searchsorted(gstart, rem, side="right") - 1)
+        bx = rem - int(gstart[g])
+        rows = lens[4 * g: 4 * g + 4]
+        out[j] = min(4, nlev - 4 * bz) * int(np.clip(rows - 4 * bx, 0, 4).sum())
+    return out

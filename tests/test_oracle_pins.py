@@ -447,3 +447,109 @@ def test_f16_hand_values():
     assert [int(g) for g in got] == list(cases.values())
     back = oracle.f16_restore(got)
     assert back[0] == 1.0 and back[5] == 2.0 ** -24 and np.isinf(back[4])
+
+
+# ---------------------------------------------------------------------------
+# Scatter and sampling helpers of the oracle, each against an independent
+# formulation: numpy slicing of the per-block decode, or the whole-buffer
+# functions pinned above
+# ---------------------------------------------------------------------------
+
+def _scatter_blocks(blocks, shape):
+    """Place per-block values (nb, 64; index 16 z + 4 y + x) into an array of
+    `shape` (nz, ny, nx) by numpy reshapes, blocks x-fastest; padding dropped."""
+    nz, ny, nx = shape
+    nbz, nby, nbx = -(-nz // 4), -(-ny // 4), -(-nx // 4)
+    full = blocks.reshape(nbz, nby, nbx, 4, 4, 4).transpose(0, 3, 1, 4, 2, 5)
+    return full.reshape(4 * nbz, 4 * nby, 4 * nbx)[:nz, :ny, :nx]
+
+
+@pytest.mark.parametrize("shape", [(6, 9, 7), (4, 4, 4), (1, 5, 13), (9, 1, 2)])
+def test_regular_decode_scatter_and_sentinels(shape):
+    """orc_decode_regular puts every real value where numpy slicing of the
+    per-block decode puts it (no axis swap, no padding written over edge
+    values) and writes nothing else: in a strided destination every element
+    between and around the view keeps its sentinel."""
+    rng = np.random.default_rng(sum(shape) + 31)
+    nz, ny, nx = shape
+    a = (280 + 15 * rng.standard_normal(shape)).astype(np.float32)
+    sx, sy = 2, 2 * nx + 3
+    sz = sy * (ny + 1) + 5
+    L = oracle.lib()
+    for rate in (8, 32):
+        words = oracle.encode_regular(a, rate)
+        want = _scatter_blocks(oracle.decode_blocks(words, rate), shape)
+        buf = np.full(sz * nz + 7, -7.0, np.float32)
+        L.orc_decode_regular(words, nx, ny, nz, sx, sy, sz, rate, buf)
+        idx = (np.arange(nz)[:, None, None] * sz + np.arange(ny)[None, :, None] * sy
+               + np.arange(nx)[None, None, :] * sx)
+        assert np.array_equal(buf[idx].view(np.uint32), want.view(np.uint32)), rate
+        outside = np.ones(buf.size, bool)
+        outside[idx.reshape(-1)] = False
+        assert (buf[outside] == -7.0).all(), rate
+        if rate == 32:
+            # near-lossless at rate 32 (every value within 2^(emax-20) of its input)
+            emax = np.frexp(np.abs(a).max())[1]
+            assert np.abs(buf[idx].astype(np.float64) - a).max() <= 2.0 ** (emax - 20)
+
+
+def test_decode_sample_matches_decode_unpack():
+    """Every block decoded on its own (with the destination offset of each of
+    its values and an in-range flag) agrees with the whole-buffer decode, and
+    the in-range values cover every point of the chunks exactly once."""
+    cs = W.reduced_grid_chunkset(n_half=20, nlev=6, nchunks=4)
+    rng = np.random.default_rng(32)
+    src = (280 + 15 * rng.standard_normal(cs.buffer_elems)).astype(np.float32)
+    for rate in (8, 16):
+        words = oracle.pack_encode(cs, src, rate)
+        dst = np.full(cs.buffer_elems, np.nan, np.float32)
+        oracle.decode_unpack(cs, words, rate, dst)
+        nb = int(oracle.chunk_blocks(cs).sum())
+        vals, pos, inside = oracle.decode_sample(cs, words, rate, np.arange(nb))
+        assert int(inside.sum()) == cs.buffer_elems == cs.values()
+        p = pos[inside]
+        assert np.array_equal(np.sort(p), np.arange(cs.buffer_elems))
+        assert np.array_equal(vals[inside].view(np.uint32), dst[p].view(np.uint32))
+        # each block's values in block order equal the per-block decoder's
+        per_block = oracle.decode_blocks(words, rate).reshape(nb, 64)
+        assert np.array_equal(vals.view(np.uint32), per_block.view(np.uint32))
+
+
+def test_pack_encode_var_sample_matches_whole_stream():
+    """Sampled variable-size blocks equal the same blocks cut out of the whole
+    stream at the offsets its per-block word counts give."""
+    cs = W.reduced_grid_chunkset(n_half=20, nlev=6, nchunks=4)
+    rng = np.random.default_rng(33)
+    src = np.cumsum(rng.standard_normal(cs.buffer_elems)).astype(np.float32)
+    for mp, me, cap in ((32, oracle.accuracy_minexp(1e-2), 16), (12, oracle.MINEXP_NONE, 32)):
+        words, nd, toff = oracle.pack_encode_var(cs, src, mp, me, cap)
+        start = np.concatenate([[0], np.cumsum(nd.astype(np.int64))])
+        ids = np.unique(np.concatenate([rng.integers(0, nd.size, 60), [0, nd.size - 1]]))
+        sw, bits, pos, inside = oracle.pack_encode_var_sample(cs, src, mp, me, cap, ids)
+        for j, b in enumerate(ids):
+            k = int(nd[b])
+            assert (int(bits[j]) + 31) // 32 == k
+            got = sw[j].view(np.uint32)
+            assert np.array_equal(got[:k], words[start[b]:start[b] + k]), (mp, b)
+            assert not got[k:].any()
+        assert (inside.sum(1) > 0).all()
+        assert np.isin(pos[inside], np.arange(cs.buffer_elems)).all()
+
+
+def test_in_range_counts_from_geometry():
+    """The test-side geometry count of real values per block (written from the
+    chunk layout) agrees with the in-range flags the oracle's sampler reports,
+    on ragged reduced-grid chunks and on a regular array with partial blocks."""
+    from _blocks import real_values
+    lens = np.array([5, 9, 3, 11, 7, 2, 6])
+    offs = np.concatenate([[1], 1 + np.cumsum(lens)[:-1] + 3 * np.arange(1, 7)])
+    odd = W.ChunkSet(np.array([0, 2]), np.array([200, 203]), np.array([6, 3]),
+                     np.array([0, 5, 7]), np.concatenate([offs[:5], offs[5:] - 2]), lens, 1300)
+    for cs in (W.reduced_grid_chunkset(n_half=20, nlev=6, nchunks=4),
+               W.reduced_grid_chunkset(n_half=12, nlev=5, nchunks=3), odd,
+               W.regular_chunkset(7, 10, 13)):
+        nb = int(oracle.chunk_blocks(cs).sum())
+        words = np.zeros(nb * 8, np.uint64)
+        _, _, inside = oracle.decode_sample(cs, words, 8, np.arange(nb))
+        assert np.array_equal(inside.sum(1), real_values(cs, np.arange(nb)))
+        assert int(real_values(cs, np.arange(nb)).sum()) == cs.values()
