@@ -1,17 +1,19 @@
 """Benchmark: fixed-rate ZFP pack+encode / decode+unpack of one GPU's
-z->lambda transpose buffer on one MI355X.
+transpose buffers on one MI355X.
 
-Workload (default): one GPU's share of a 64-rank z->lambda transposition at
-O1280-like resolution -- 4 float32 fields (u, v, T, q) x 137 levels x 64
-latitude rows x 1612 points = 56,536,064 values (226.1 MB), cut into 64
-per-destination chunks, synthetic T42 spectral fields (seeded).
+Headline workload: the large single-GPU buffer -- one float32 field on the
+O2560-like reduced octahedral grid (5120 latitude rows, 26,306,560 points per
+level) x 90 levels = 2,367,590,400 values (9.47 GB), one chunk, synthetic
+T42 spectral field (seeded; levels 8..89 repeat the generated levels 0..7).
 
 A step is one pass of the method over that buffer at rate 16: fused
 pack+encode into the send buffer, then fused decode+unpack into the receive
-layout.  `value` = float32 input bytes / step time (encode + decode), with the
-inputs resident in HBM.  Several input/output buffer sets are rotated so that
-the 256 MB last-level cache cannot hold a step's working set.  Rate 8 and the
-float16 comparator are timed the same way and reported beside it.
+layout.  Each step decodes the stream the previous step encoded (two stream
+buffers alternate), as a receiver decodes a message that arrived from the
+network.  `value` = float32 input bytes x steps / wall time of the timed
+steps, with the inputs resident in HBM.  Rate 8 and the float16 comparator
+are timed on the same buffer; the z->lambda share (226 MB, 64 chunks), the
+small regular field (256 KiB) and the other legs are reported beside it.
 
 One JSON line on stdout.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -36,25 +38,33 @@ VALU_SIMD_CYCLES_PER_S = 1024 * 2.4e9  # 256 CUs x 4 SIMDs at 2.4 GHz
 KERNEL_SOURCES = ("paper_2609_24294_amd/csrc/kernels.hip",
                   "paper_2609_24294_amd/csrc/block_codec.hpp",
                   "paper_2609_24294_amd/csrc/internal.hpp")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "zlambda_share_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "o2560_l90_hbm_traffic.md")
+
+LEGS = ("share", "small", "accuracy", "variable", "sensitivity", "pipeline", "fourier",
+        "batching", "serving", "cpu")
 
 
-def measured_traffic(kernel: str, rate: int):
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, rate: int, path: str = TRAFFIC_PROFILE):
     """HBM bytes per launch of `kernel` at `rate` from the committed counter
     passes (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
     or None when there are none or the kernel sources changed since."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
         block = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-        h = hashlib.sha256()
-        for p in KERNEL_SOURCES:
-            with open(os.path.join(ROOT, p), "rb") as f:
-                h.update(f.read())
-        if h.hexdigest()[:16] != block["source_hash"]:
+        if kernel_source_hash() != block["source_hash"]:
             return None
         k = block["kernels"][kernel][str(rate)]
         return {"bytes": k["read_bytes"] + k["write_bytes"], "read": k["read_bytes"],
-                "write": k["write_bytes"], "valu": k.get("valu_insts")}
+                "write": k["write_bytes"], "valu": k.get("valu_insts"),
+                "waves": k.get("waves")}
     except (OSError, IndexError, KeyError, ValueError):
         return None
 
@@ -67,36 +77,24 @@ def log(msg: str) -> None:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rate", type=int, default=16)
-    ap.add_argument("--sets", type=int, default=3, help="rotated buffer sets")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip rate-8 and f16 legs")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated legs besides the headline (" + ",".join(LEGS) +
+                         "), 'all' or 'none'")
+    ap.add_argument("--sets", type=int, default=3, help="rotated buffer sets (z->lambda share)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter calibration)")
-    ap.add_argument("--no-accuracy", action="store_true", help="skip the error report")
-    ap.add_argument("--no-batching", action="store_true",
-                    help="skip the batched vs per-chunk comparison (lambda->theta buffer)")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving latency leg")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the O2560 x 90 levels (9.47 GB) throughput leg")
-    ap.add_argument("--no-variable", action="store_true",
-                    help="skip the fixed-precision / fixed-accuracy leg")
-    ap.add_argument("--no-pipeline", action="store_true",
-                    help="skip the chunk-pipelined send/receive over a host link")
-    ap.add_argument("--no-fourier", action="store_true",
-                    help="skip the Fourier-space lambda->theta buffer leg")
-    ap.add_argument("--no-sensitivity", action="store_true",
-                    help="skip the data-roughness leg (T255 and white noise)")
     ap.add_argument("--serving-requests", type=int, default=10000)
     return ap.parse_args()
 
 
 def timed_loop(fn_list, steps, warmup, torch, detail=False):
     """Run warmup + steps iterations of a list of launch callables on the
-    current stream; per callable, the mean event-timed duration (ms) (and,
-    with detail, the per-step durations)."""
+    current stream (the stream the library launches on); per callable, the
+    mean event-timed duration (ms) (and, with detail, the per-step
+    durations).  Step i of a callable list runs f(i) for each f in order."""
     s = torch.cuda.current_stream()
     for i in range(warmup):
         for f in fn_list:
@@ -109,7 +107,7 @@ def timed_loop(fn_list, steps, warmup, torch, detail=False):
         e = evs[i]
         e[0].record(s)
         for j, f in enumerate(fn_list):
-            f(i)
+            f(warmup + i)
             e[j + 1].record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -121,89 +119,76 @@ def timed_loop(fn_list, steps, warmup, torch, detail=False):
     return wall, per
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path.", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
+def hbm_frac(nbytes, ms):
+    return round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
-    from paper_2609_24294_amd import workloads as W
-    from paper_2609_24294_amd import zfpx
 
+def large_buffer(torch, W):
+    """The O2560 x 90 field on the device (levels 8..89 repeat 0..7: a
+    4-level block never straddles a repeat, so every block has the
+    generator's level-to-level statistics)."""
+    log("generating the O2560 x 90 field (8 levels, repeated on the device)")
+    base = W.large_field_levels(8)
+    cs = W.large_chunkset()
+    npts = base.shape[1]
+    nlev = cs.buffer_elems // npts
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    rate = args.rate
-    log("generating the z->lambda share (4 fields x 137 x 64 x 1612)")
-    x32, _ = W.zlambda_fields(want_f64=False)
-    cs = W.zlambda_chunkset()
+    b = torch.from_numpy(base.reshape(-1)).to(dev)
+    src = torch.empty(cs.buffer_elems, dtype=torch.float32, device=dev)
+    for k in range(0, nlev, 8):
+        n = min(8, nlev - k) * npts
+        src[k * npts: k * npts + n] = b[:n]
+    del b
+    return cs, src, base, npts, nlev
+
+
+def headline_report(args, torch, zfpx, W):
+    """O2560 x 90 levels (9.47 GB, one chunk): `steps` timed steps of encode
+    then decode at the headline rate, each decoding the previous step's
+    stream; rate 8 and float16 on the same buffer."""
+    cs, src, base, npts, nlev = large_buffer(torch, W)
+    del base
     plan = zfpx.Plan.from_chunkset(cs)
-    nvals = plan.nvalues
-    nblocks = plan.nblocks
+    nvals, nblocks = plan.nvalues, plan.nblocks
     in_bytes = 4 * nvals
-    nsets = max(1, args.sets)
-    src = [torch.from_numpy(x32.reshape(-1)).to(dev) for _ in range(nsets)]
-    del x32
-    send = {r: [torch.empty(nblocks * r, dtype=torch.int64, device=dev) for _ in range(nsets)]
-            for r in (rate, 8) if r}
-    dst = [torch.empty_like(src[0]) for _ in range(nsets)]
-
-    def enc(r):
-        return lambda i: zfpx.zfpx_pack_encode(plan, src[i % nsets], r, send[r][i % nsets])
-
-    def dec(r):
-        return lambda i: zfpx.zfpx_decode_unpack(plan, send[r][i % nsets], r, dst[i % nsets])
-
-    log(f"timing rate {rate}: {args.warmup} warmup + {args.steps} steps")
-    wall, (t_enc, t_dec), each = timed_loop([enc(rate), dec(rate)], args.steps, args.warmup,
-                                            torch, detail=True)
-    spread = {f"{name}_ms_{stat}": round(float(f(each[j])), 4)
-              for j, name in enumerate(("encode", "decode"))
-              for stat, f in (("median", statistics.median), ("min", min))}
-    ms_per_step = 1000.0 * wall / args.steps
-    value = in_bytes * args.steps / wall / 1e9
-
-    coded = nblocks * 8 * rate
-    alg_enc = in_bytes + coded   # read float32, write the stream
-    alg_dec = coded + in_bytes   # read the stream, write float32
-    enc_gbs = alg_enc / (t_enc * 1e-3) / 1e9
-    dec_gbs = alg_dec / (t_dec * 1e-3) / 1e9
-    dominant = "pack_encode" if t_enc >= t_dec else "decode_unpack"
-    t_dom = max(t_enc, t_dec)
-    alg_dom = alg_enc if t_enc >= t_dec else alg_dec
-    achieved = alg_dom / (t_dom * 1e-3) / 1e9
-    traffic = measured_traffic(dominant, rate)
-
-    # bit-exact round trip is checked by the tests; here only a cheap sanity check
-    torch.cuda.synchronize()
-
-    extras = {}
-    if not args.no_extras:
-        log("timing rate 8 and the float16 comparator")
-        _, (e8, d8) = timed_loop([enc(8), dec(8)], max(5, args.steps // 2), 2, torch)
-        c8 = nblocks * 8 * 8
-        h = [torch.empty(nvals, dtype=torch.int16, device=dev) for _ in range(nsets)]
-        ft = lambda i: zfpx.f16_truncate(src[i % nsets], h[i % nsets])
-        fr = lambda i: zfpx.f16_restore(h[i % nsets], dst[i % nsets])
-        _, (tt, tr) = timed_loop([ft, fr], max(5, args.steps // 2), 2, torch)
-        extras = {
-            "rate8": {"encode_ms": round(e8, 4), "decode_ms": round(d8, 4),
-                      "gbs_fp32_input": round(in_bytes / ((e8 + d8) * 1e-3) / 1e9, 1),
-                      "encode_hbm_frac": round((in_bytes + c8) / (e8 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                      "decode_hbm_frac": round((in_bytes + c8) / (d8 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                      "bytes_reduction": round(in_bytes / c8, 3)},
-            "f16": {"truncate_ms": round(tt, 4), "restore_ms": round(tr, 4),
-                    "gbs_fp32_input": round(in_bytes / ((tt + tr) * 1e-3) / 1e9, 1),
-                    "truncate_hbm_frac": round(6 * nvals / (tt * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                    "bytes_reduction": 2.0},
-        }
-        del h
-        if rate == 16:
-            extras["transpose_model"] = transpose_model_report(
-                in_bytes, t_enc, t_dec, e8, d8, tt, tr)
-
+    dev = src.device
+    dst = torch.empty_like(src)
+    out = {"workload": f"O2560 reduced grid ({npts} points/level, 5120 rows) x {nlev} levels "
+                       f"f32 ({in_bytes / 1e9:.2f} GB), one chunk",
+           "values": nvals, "blocks": nblocks,
+           "data": "synthetic T42 field; levels 8..89 repeat the generated levels 0..7"}
+    res = {}
+    for rate in ((args.rate, 8) if args.rate != 8 else (8,)):
+        send = [torch.empty(nblocks * rate, dtype=torch.int64, device=dev) for _ in range(2)]
+        enc = lambda i, r=rate, sd=send: zfpx.zfpx_pack_encode(plan, src, r, sd[i % 2])
+        dec = lambda i, r=rate, sd=send: zfpx.zfpx_decode_unpack(plan, sd[(i - 1) % 2], r, dst)
+        steps = args.steps if rate == args.rate else max(5, args.steps // 2)
+        log(f"headline: rate {rate}, {max(2, args.warmup)} warmup + {steps} steps")
+        wall, (te, td), each = timed_loop([enc, dec], steps, max(2, args.warmup), torch,
+                                          detail=True)
+        alg = in_bytes + nblocks * 8 * rate
+        res[rate] = dict(wall=wall, steps=steps, te=te, td=td, alg=alg)
+        out[f"rate{rate}"] = {
+            "encode_ms": round(te, 4), "decode_ms": round(td, 4),
+            **{f"{name}_ms_{stat}": round(float(f(each[j])), 4)
+               for j, name in enumerate(("encode", "decode"))
+               for stat, f in (("median", statistics.median), ("min", min))},
+            "gbs_fp32_input": round(in_bytes / ((te + td) * 1e-3) / 1e9, 1),
+            "encode_gbs_fp32": round(in_bytes / (te * 1e-3) / 1e9, 1),
+            "decode_gbs_fp32": round(in_bytes / (td * 1e-3) / 1e9, 1),
+            "encode_hbm_frac": hbm_frac(alg, te), "decode_hbm_frac": hbm_frac(alg, td),
+            "algorithmic_bytes_per_launch": alg,
+            "bytes_reduction": round(in_bytes / (nblocks * 8 * rate), 3)}
+        del send
+    h = torch.empty(nvals, dtype=torch.int16, device=dev)
+    ft = lambda i: zfpx.f16_truncate(src, h)
+    fr = lambda i: zfpx.f16_restore(h, dst)
+    _, (tt, tr) = timed_loop([ft, fr], max(5, args.steps // 2), 2, torch)
+    out["f16"] = {"truncate_ms": round(tt, 4), "restore_ms": round(tr, 4),
+                  "gbs_fp32_input": round(in_bytes / ((tt + tr) * 1e-3) / 1e9, 1),
+                  "truncate_hbm_frac": hbm_frac(6 * nvals, tt),
+                  "restore_hbm_frac": hbm_frac(6 * nvals, tr), "bytes_reduction": 2.0}
+    del h
     if args.copy_calibration:
         # known traffic for the counter passes: 256 MiB read and 256 MiB
         # written by a plain elementwise kernel (and by the runtime's copy)
@@ -214,102 +199,235 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    # precision mode 16 (cap 16): three encode launches, one decode launch
+    log("headline buffer: precision 16 (variable size)")
+    w, nd, to = zfpx.zfpx_plan_encode_var(plan, src, 16, zfpx.MINEXP_NONE, 16)
+    enc = lambda i: zfpx.zfpx_plan_encode_var(plan, src, 16, zfpx.MINEXP_NONE, 16, w, nd, to)
+    dec = lambda i: zfpx.zfpx_plan_decode_var(plan, w, nd, to, 16, zfpx.MINEXP_NONE, 16, dst)
+    _, (te, td) = timed_loop([enc, dec], 5, 1, torch)
+    torch.cuda.synchronize()
+    coded = 4 * int(to[-1].item()) + plan.nblocks + 8 * to.numel()
+    out["precision16"] = {"encode_ms": round(te, 3), "decode_ms": round(td, 3),
+                          "bits_per_value": round(8 * coded / nvals, 3),
+                          "encode_hbm_frac": hbm_frac(in_bytes + coded, te),
+                          "decode_hbm_frac": hbm_frac(in_bytes + coded, td)}
+    del w, nd, to, src, dst
+    torch.cuda.empty_cache()
+    return out, res, in_bytes
 
-    variable = None
-    if not args.no_variable:
-        variable = variable_report(plan, src, dst, nvals, nblocks, max(5, args.steps // 2),
-                                   torch, zfpx, W)
 
-    pipeline = None
-    if not args.no_pipeline:
-        pipeline = pipeline_report(plan, src[0], nvals, nblocks, torch, zfpx)
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    legs = (set(LEGS) if args.legs == "all" else
+            set() if args.legs == "none" else set(args.legs.split(",")))
+    unknown = legs - set(LEGS)
+    if unknown:
+        print(f"unknown legs {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
+    import torch
 
-    fourier = None
-    if not args.no_fourier:
-        fourier = fourier_report(max(5, args.steps // 2), torch, zfpx, W)
+    from paper_2609_24294_amd import workloads as W
+    from paper_2609_24294_amd import zfpx
 
-    accuracy = None
-    if not args.no_accuracy:
-        accuracy = accuracy_report(plan, src[0], dst[0], nvals, nblocks, torch, zfpx, W)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rate = args.rate
 
-    # last user of the share's buffers: it overwrites them with other data
-    sensitivity = None
-    if not args.no_sensitivity:
-        sensitivity = sensitivity_report(plan, src, dst, nblocks, max(5, args.steps // 2),
-                                         torch, zfpx, W)
+    head, res, in_bytes = headline_report(args, torch, zfpx, W)
+    r = res[rate]
+    ms_per_step = 1000.0 * r["wall"] / r["steps"]
+    value = in_bytes * r["steps"] / r["wall"] / 1e9
+    t_enc, t_dec = r["te"], r["td"]
+    dominant = "pack_encode" if t_enc >= t_dec else "decode_unpack"
+    t_dom = max(t_enc, t_dec)
+    achieved = r["alg"] / (t_dom * 1e-3) / 1e9
+    traffic = measured_traffic(dominant, rate)
 
-    large = None
-    if not args.no_large:
-        del src, dst, send
+    share = small = accuracy = variable = sensitivity = pipeline = fourier = None
+    batching = serving = cpu = model = None
+    if "share" in legs or "variable" in legs or "pipeline" in legs or "sensitivity" in legs \
+            or "accuracy" in legs:
+        share_ctx = share_buffers(args, torch, zfpx, W)
+        if "share" in legs:
+            share = share_report(args, share_ctx, torch, zfpx)
+        if "variable" in legs:
+            variable = variable_report(share_ctx["plan"], share_ctx["src"], share_ctx["dst"],
+                                       share_ctx["nvals"], share_ctx["nblocks"],
+                                       max(5, args.steps // 2), torch, zfpx, W)
+        if "pipeline" in legs:
+            pipeline = pipeline_report(share_ctx["plan"], share_ctx["src"][0], share_ctx["nvals"],
+                                       share_ctx["nblocks"], torch, zfpx)
+        if "accuracy" in legs:
+            accuracy = accuracy_report(share_ctx["plan"], share_ctx["src"][0],
+                                       share_ctx["dst"][0], share_ctx["nvals"],
+                                       share_ctx["nblocks"], torch, zfpx, W)
+        # last user of the share's buffers: it overwrites them with other data
+        if "sensitivity" in legs:
+            sensitivity = sensitivity_report(share_ctx["plan"], share_ctx["src"], share_ctx["dst"],
+                                             share_ctx["nblocks"], max(5, args.steps // 2),
+                                             torch, zfpx, W)
+        del share_ctx
         torch.cuda.empty_cache()
-        large = large_report(torch, zfpx, W)
-        src = dst = send = None
-
-    batching = None
-    if not args.no_batching:
-        del src, dst, send
+    if "small" in legs:
+        small = small_report(torch, zfpx, W)
+    if "fourier" in legs:
+        fourier = fourier_report(max(5, args.steps // 2), torch, zfpx, W)
+    if rate == 16 and 8 in res:
+        r8 = res[8]
+        f16 = head["f16"]
+        model = transpose_model_report(in_bytes, t_enc, t_dec, r8["te"], r8["td"],
+                                       f16["truncate_ms"], f16["restore_ms"])
+    if "batching" in legs:
         torch.cuda.empty_cache()
         batching = batching_report(torch, zfpx, W)
-        src = dst = send = None
-
-    serving = None
-    if not args.no_serving:
+    if "serving" in legs:
         torch.cuda.empty_cache()
         try:
             serving = serving_report(torch, zfpx, W, args.serving_requests)
         except zfpx.ZfpxError as e:
             serving = {"error": str(e)}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cs, rate)
+    if "cpu" in legs:
+        cpu = cpu_baseline(rate)
 
     out = {
         "metric": "encode+decode GB/s of fp32 input and % HBM peak at rate 8/16; p99 request latency",
         "value": round(value, 2),
         "unit": "GB/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": r["steps"],
+        "warmup": max(2, args.warmup),
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32->int32 codec",
         "data": "synthetic T42 spherical-harmonic fields (seeded); DYAMOND not available",
-        "config": {"workload": "z->lambda transpose share, 4x137x64x1612 f32 (226.1 MB), "
-                               "64 chunks", "rate": rate, "values": nvals, "blocks": nblocks,
-                   "buffer_sets": nsets},
+        "config": {"workload": "O2560 reduced octahedral grid x 90 levels, one float32 field "
+                               "(2,367,590,400 values, 9.47 GB), one chunk", "rate": rate,
+                   "values": head["values"], "blocks": head["blocks"],
+                   "stream_buffers": 2},
         "encode_ms": round(t_enc, 4),
         "decode_ms": round(t_dec, 4),
-        **spread,
-        "encode_hbm_frac": round(enc_gbs / HBM_PEAK_GBS, 4),
-        "decode_hbm_frac": round(dec_gbs / HBM_PEAK_GBS, 4),
-        "bytes_reduction": round(in_bytes / coded, 3),
+        "encode_hbm_frac": hbm_frac(r["alg"], t_enc),
+        "decode_hbm_frac": hbm_frac(r["alg"], t_dec),
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "algorithmic_bytes": alg_dom,
+                     "algorithmic_bytes": r["alg"],
                      "traffic": traffic["bytes"] if traffic else None,
                      "traffic_read_write": [traffic["read"], traffic["write"]] if traffic else None,
                      # the same kernel against its instruction-issue ceiling: VALU
                      # wavefront instructions (counter pass) x 4 cycles each on a
                      # 16-lane SIMD, over 1024 SIMDs x 2.4 GHz x the launch time
+                     "valu_per_tile": (round(traffic["valu"] / traffic["waves"], 1)
+                                       if traffic and traffic.get("valu") and traffic.get("waves")
+                                       else None),
                      "valu_issue_frac": (round(traffic["valu"] * 4 / (VALU_SIMD_CYCLES_PER_S
                                                                      * t_dom * 1e-3), 4)
                                          if traffic and traffic["valu"] else None)},
         "cpu_baseline": cpu,
-        **extras,
+        "headline": head,
+        "share": share,
+        "small": small,
+        "transpose_model": model,
         "accuracy": accuracy,
         "variable": variable,
         "sensitivity": sensitivity,
         "pipeline": pipeline,
         "fourier": fourier,
-        "large": large,
         "batching": batching,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def share_buffers(args, torch, zfpx, W):
+    """The z->lambda share on the device, in `sets` rotated buffer sets."""
+    log("generating the z->lambda share (4 fields x 137 x 64 x 1612)")
+    x32, _ = W.zlambda_fields(want_f64=False)
+    cs = W.zlambda_chunkset()
+    plan = zfpx.Plan.from_chunkset(cs)
+    dev = torch.device("cuda:0")
+    nsets = max(2, args.sets)
+    src = [torch.from_numpy(x32.reshape(-1)).to(dev) for _ in range(nsets)]
+    dst = [torch.empty_like(src[0]) for _ in range(nsets)]
+    return {"cs": cs, "plan": plan, "src": src, "dst": dst, "nsets": nsets,
+            "nvals": plan.nvalues, "nblocks": plan.nblocks}
+
+
+def share_report(args, ctx, torch, zfpx):
+    """z->lambda share (226.1 MB, 64 chunks): encode and decode at rates 16
+    and 8 over rotated buffer sets whose combined size exceeds the 256 MB
+    last-level cache; step i decodes the stream step i-1 encoded (another
+    set), and float16 the same way."""
+    plan, src, dst, nsets = ctx["plan"], ctx["src"], ctx["dst"], ctx["nsets"]
+    nvals, nblocks = ctx["nvals"], ctx["nblocks"]
+    in_bytes = 4 * nvals
+    out = {"workload": "z->lambda transpose share, 4x137x64x1612 f32 (226.1 MB), 64 chunks",
+           "buffer_sets": nsets}
+    for rate in (16, 8):
+        send = [torch.empty(nblocks * rate, dtype=torch.int64, device=src[0].device)
+                for _ in range(nsets)]
+        enc = lambda i, r=rate, sd=send: zfpx.zfpx_pack_encode(plan, src[i % nsets], r,
+                                                              sd[i % nsets])
+        dec = lambda i, r=rate, sd=send: zfpx.zfpx_decode_unpack(plan, sd[(i - 1) % nsets], r,
+                                                                dst[(i - 1) % nsets])
+        steps = max(10, args.steps)
+        log(f"share: rate {rate}")
+        _, (te, td), each = timed_loop([enc, dec], steps, max(nsets, 2), torch, detail=True)
+        alg = in_bytes + nblocks * 8 * rate
+        out[f"rate{rate}"] = {
+            "encode_ms": round(te, 4), "decode_ms": round(td, 4),
+            **{f"{name}_ms_{stat}": round(float(f(each[j])), 4)
+               for j, name in enumerate(("encode", "decode"))
+               for stat, f in (("median", statistics.median), ("min", min))},
+            "gbs_fp32_input": round(in_bytes / ((te + td) * 1e-3) / 1e9, 1),
+            "encode_hbm_frac": hbm_frac(alg, te), "decode_hbm_frac": hbm_frac(alg, td),
+            "bytes_reduction": round(in_bytes / (nblocks * 8 * rate), 3)}
+        del send
+    h = [torch.empty(nvals, dtype=torch.int16, device=src[0].device) for _ in range(nsets)]
+    ft = lambda i: zfpx.f16_truncate(src[i % nsets], h[i % nsets])
+    fr = lambda i: zfpx.f16_restore(h[(i - 1) % nsets], dst[(i - 1) % nsets])
+    _, (tt, tr) = timed_loop([ft, fr], max(10, args.steps), max(nsets, 2), torch)
+    out["f16"] = {"truncate_ms": round(tt, 4), "restore_ms": round(tr, 4),
+                  "gbs_fp32_input": round(in_bytes / ((tt + tr) * 1e-3) / 1e9, 1),
+                  "truncate_hbm_frac": hbm_frac(6 * nvals, tt),
+                  "restore_hbm_frac": hbm_frac(6 * nvals, tr), "bytes_reduction": 2.0}
+    del h
+    return out
+
+
+def small_report(torch, zfpx, W, reps=200):
+    """The small regular field (T42, f32[8][64][128], 65,536 values, 256 KiB)
+    timed in full at rates 8/16/32 and float16: each launch is a few
+    microseconds and the data stay in the last-level cache, so this is a
+    launch-latency figure, not an HBM one."""
+    log("small: regular 8 x 64 x 128 field, all rates")
+    x32, _ = W.small_field()
+    dev = torch.device("cuda:0")
+    src = torch.from_numpy(x32).to(dev)
+    dst = torch.empty_like(src)
+    in_bytes = 4 * x32.size
+    out = {"workload": "regular 64 x 128 Gauss-Legendre grid x 8 levels f32 (256 KiB), T42",
+           "values": int(x32.size)}
+    for rate in (8, 16, 32):
+        words = zfpx.zfpx_encode_fixed_rate(src, rate)
+        enc = lambda i, r=rate, w=words: zfpx.zfpx_encode_fixed_rate(src, r, w)
+        dec = lambda i, r=rate, w=words: zfpx.zfpx_decode_fixed_rate(w, r, dst)
+        _, (te, td) = timed_loop([enc, dec], reps, 10, torch)
+        out[f"rate{rate}"] = {"encode_us": round(te * 1e3, 2), "decode_us": round(td * 1e3, 2),
+                              "gbs_fp32_input": round(in_bytes / ((te + td) * 1e-3) / 1e9, 1),
+                              "bytes_reduction": round(in_bytes / (words.numel() * 8), 3)}
+    h = torch.empty(x32.size, dtype=torch.int16, device=dev)
+    ft = lambda i: zfpx.f16_truncate(src.reshape(-1), h)
+    fr = lambda i: zfpx.f16_restore(h, dst.reshape(-1))
+    _, (tt, tr) = timed_loop([ft, fr], reps, 10, torch)
+    out["f16"] = {"truncate_us": round(tt * 1e3, 2), "restore_us": round(tr * 1e3, 2)}
+    return out
 
 
 def variable_report(plan, src, dst, nvals, nblocks, steps, torch, zfpx, W):
@@ -336,11 +454,12 @@ def variable_report(plan, src, dst, nvals, nblocks, steps, torch, zfpx, W):
             w, nd, to = sets[i % nsets]
             return zfpx.zfpx_plan_encode_var(plan, src[i % nsets], maxprec, minexp, cap, w, nd, to)
 
-        def dec(i):
-            w, nd, to = sets[i % nsets]
-            return zfpx.zfpx_plan_decode_var(plan, w, nd, to, maxprec, minexp, cap, dst[i % nsets])
+        def dec(i):  # the set the previous step encoded
+            w, nd, to = sets[(i - 1) % nsets]
+            return zfpx.zfpx_plan_decode_var(plan, w, nd, to, maxprec, minexp, cap,
+                                             dst[(i - 1) % nsets])
 
-        _, (te, td) = timed_loop([enc, dec], steps, 2, torch)
+        _, (te, td) = timed_loop([enc, dec], steps, nsets, torch)
         torch.cuda.synchronize()
         w, nd, to = sets[0]
         words = int(to[-1].item())
@@ -393,8 +512,9 @@ def sensitivity_report(plan, src, dst, nblocks, steps, torch, zfpx, W):
             send = [torch.empty(nblocks * rate, dtype=torch.int64, device=src[0].device)
                     for _ in range(nsets)]
             enc = lambda i: zfpx.zfpx_pack_encode(plan, src[i % nsets], rate, send[i % nsets])
-            dec = lambda i: zfpx.zfpx_decode_unpack(plan, send[i % nsets], rate, dst[i % nsets])
-            _, (te, td) = timed_loop([enc, dec], steps, 2, torch)
+            dec = lambda i: zfpx.zfpx_decode_unpack(plan, send[(i - 1) % nsets], rate,
+                                                    dst[(i - 1) % nsets])
+            _, (te, td) = timed_loop([enc, dec], steps, nsets, torch)
             alg = 4 * nvals + nblocks * 8 * rate
             r[f"rate{rate}"] = {"encode_ms": round(te, 4), "decode_ms": round(td, 4),
                                 "encode_hbm_frac": round(alg / (te * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -522,8 +642,9 @@ def fourier_report(steps, torch, zfpx, W, nsets=3):
     for rate in (16, 8):
         send = [torch.empty(nblocks * rate, dtype=torch.int64, device=dev) for _ in range(nsets)]
         enc = lambda i: zfpx.zfpx_pack_encode(plan, src[i % nsets], rate, send[i % nsets])
-        dec = lambda i: zfpx.zfpx_decode_unpack(plan, send[i % nsets], rate, dst[i % nsets])
-        _, (te, td) = timed_loop([enc, dec], steps, 2, torch)
+        dec = lambda i: zfpx.zfpx_decode_unpack(plan, send[(i - 1) % nsets], rate,
+                                                dst[(i - 1) % nsets])
+        _, (te, td) = timed_loop([enc, dec], steps, nsets, torch)
         zfpx.zfpx_decode_unpack(plan, send[0], rate, dst[0])
         alg = 4 * nvals + nblocks * 8 * rate
         out[f"rate{rate}"] = {"encode_ms": round(te, 4), "decode_ms": round(td, 4),
@@ -540,9 +661,9 @@ def fourier_report(steps, torch, zfpx, W, nsets=3):
         sets = [zfpx.zfpx_plan_encode_var(plan, src[i], maxprec, minexp, cap) for i in range(nsets)]
         enc = lambda i: zfpx.zfpx_plan_encode_var(plan, src[i % nsets], maxprec, minexp, cap,
                                                   *sets[i % nsets])
-        dec = lambda i: zfpx.zfpx_plan_decode_var(plan, *sets[i % nsets], maxprec, minexp, cap,
-                                                  dst[i % nsets])
-        _, (te, td) = timed_loop([enc, dec], steps, 2, torch)
+        dec = lambda i: zfpx.zfpx_plan_decode_var(plan, *sets[(i - 1) % nsets], maxprec, minexp,
+                                                  cap, dst[(i - 1) % nsets])
+        _, (te, td) = timed_loop([enc, dec], steps, nsets, torch)
         torch.cuda.synchronize()
         w, nd, to = sets[0]
         zfpx.zfpx_plan_decode_var(plan, w, nd, to, maxprec, minexp, cap, dst[0])
@@ -575,95 +696,45 @@ def transpose_model_report(in_bytes, e16, d16, e8, d8, tt, tr):
 
 def accuracy_report(plan, src, dst, nvals, nblocks, torch, zfpx, W):
     """Relative error of each rate and of float16 against the FP64 copy of the
-    synthetic fields (untimed), plus the bytes reduction of the buffer."""
+    synthetic fields (untimed), plus the bytes reduction of the buffer: the
+    share synthesised at T42 (the workload) and at T255 (rougher fields,
+    where rate 16 is no longer at float32's own storage error)."""
     import numpy as np
 
     from paper_2609_24294_amd import metrics
-    log("accuracy: error of rates 8/16/32 and float16 against the FP64 fields")
-    _, x64 = W.zlambda_fields(want_f64=True)
     names = ("u", "v", "T", "q")
     out = {"reference": "FP64 copy of the synthetic fields; per-block L2 relative error over "
                         "4x4x4 blocks (mean/max), global L2 error, pointwise for T and q"}
-    shape = x64.shape
-    for r in (8, 16, 32):
-        send = torch.empty(nblocks * r, dtype=torch.int64, device=src.device)
-        zfpx.zfpx_pack_encode(plan, src, r, send)
-        zfpx.zfpx_decode_unpack(plan, send, r, dst)
-        back = dst.cpu().numpy().reshape(shape)
-        out[f"rate{r}"] = {
-            "bytes_reduction": round(metrics.bytes_reduction(nvals, nblocks * 8 * r), 3),
-            **{names[f]: {k: float(f"{v:.3e}") for k, v in
-                          metrics.error_report(x64[f], back[f], pointwise=f in (2, 3)).items()}
-               for f in range(4)}}
-        del send
-    h = zfpx.f16_truncate(src)
-    back = zfpx.f16_restore(h).cpu().numpy().reshape(shape)
-    out["f16"] = {"bytes_reduction": 2.0,
-                  **{names[f]: {k: float(f"{v:.3e}") for k, v in
-                                metrics.error_report(x64[f], back[f], pointwise=f in (2, 3)).items()}
-                     for f in range(4)}}
-    x32 = src.cpu().numpy().reshape(shape)
-    out["float32_storage"] = {names[f]: float(f"{metrics.error_report(x64[f], x32[f], False)['block_mean']:.3e}")
-                              for f in range(4)}
-    return out
-
-
-def large_report(torch, zfpx, W, reps=5):
-    """Large single-GPU throughput: one float32 field on the O2560 reduced grid
-    x 90 levels (9.47 GB, one chunk), encode and decode at rates 8 and 16,
-    each against the HBM roofline."""
-    log("large: generating 8 levels of the O2560 field")
-    base = W.large_field_levels(8)
-    cs = W.large_chunkset()
-    plan = zfpx.Plan.from_chunkset(cs)
-    dev = torch.device("cuda:0")
-    npts = base.shape[1]
-    nlev = cs.buffer_elems // npts
-    b = torch.from_numpy(base.reshape(-1)).to(dev)
-    del base
-    src = torch.empty(cs.buffer_elems, dtype=torch.float32, device=dev)
-    for k in range(0, nlev, 8):  # level k repeats level k % 8
-        n = min(8, nlev - k) * npts
-        src[k * npts: k * npts + n] = b[:n]
-    del b
-    dst = torch.empty_like(src)
-    in_bytes = 4 * plan.nvalues
-    out = {"workload": f"O2560 reduced grid ({npts} points/level) x {nlev} levels f32 "
-                       f"({in_bytes / 1e9:.2f} GB), one chunk",
-           "blocks": plan.nblocks,
-           "data": "levels 8..89 repeat generated levels 0..7 (no 4-level block straddles a repeat)"}
-    for rate in (8, 16):
-        send = torch.empty(plan.nblocks * rate, dtype=torch.int64, device=dev)
-        enc = lambda i: zfpx.zfpx_pack_encode(plan, src, rate, send)
-        dec = lambda i: zfpx.zfpx_decode_unpack(plan, send, rate, dst)
-        log(f"large: rate {rate}")
-        _, (te, td) = timed_loop([enc, dec], reps, 1, torch)
-        alg = in_bytes + plan.nblocks * 8 * rate
-        out[f"rate{rate}"] = {
-            "encode_ms": round(te, 3), "decode_ms": round(td, 3),
-            "encode_gbs": round(alg / (te * 1e-3) / 1e9, 1),
-            "decode_gbs": round(alg / (td * 1e-3) / 1e9, 1),
-            "encode_hbm_frac": round(alg / (te * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "decode_hbm_frac": round(alg / (td * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "algorithmic_bytes": alg}
-        del send
-    # precision mode 16 (cap 16): three encode launches, one decode launch
-    log("large: precision 16 (variable size)")
-    w, nd, to = zfpx.zfpx_plan_encode_var(plan, src, 16, zfpx.MINEXP_NONE, 16)
-    enc = lambda i: zfpx.zfpx_plan_encode_var(plan, src, 16, zfpx.MINEXP_NONE, 16, w, nd, to)
-    dec = lambda i: zfpx.zfpx_plan_decode_var(plan, w, nd, to, 16, zfpx.MINEXP_NONE, 16, dst)
-    _, (te, td) = timed_loop([enc, dec], reps, 1, torch)
-    torch.cuda.synchronize()
-    coded = 4 * int(to[-1].item()) + plan.nblocks + 8 * to.numel()
-    out["precision16"] = {"encode_ms": round(te, 3), "decode_ms": round(td, 3),
-                          "bits_per_value": round(8 * coded / plan.nvalues, 3),
-                          "encode_hbm_frac": round((in_bytes + coded) / (te * 1e-3) / 1e9
-                                                   / HBM_PEAK_GBS, 4),
-                          "decode_hbm_frac": round((in_bytes + coded) / (td * 1e-3) / 1e9
-                                                   / HBM_PEAK_GBS, 4)}
-    del w, nd, to
-    del src, dst
-    torch.cuda.empty_cache()
+    dev = src.device
+    for L in (42, 255):
+        log(f"accuracy: T{L}, rates 8/16/32 and float16 against the FP64 fields")
+        x32, x64 = W.zlambda_fields(L=L, want_f64=True)
+        shape = x64.shape
+        d = torch.from_numpy(x32.reshape(-1)).to(dev)
+        rep = {}
+        for r in (8, 16, 32):
+            send = torch.empty(nblocks * r, dtype=torch.int64, device=dev)
+            zfpx.zfpx_pack_encode(plan, d, r, send)
+            zfpx.zfpx_decode_unpack(plan, send, r, dst)
+            back = dst.cpu().numpy().reshape(shape)
+            rep[f"rate{r}"] = {
+                "bytes_reduction": round(metrics.bytes_reduction(nvals, nblocks * 8 * r), 3),
+                **{names[f]: {k: float(f"{v:.3e}") for k, v in
+                              metrics.error_report(x64[f], back[f], pointwise=f in (2, 3)).items()}
+                   for f in range(4)}}
+            del send
+        h = zfpx.f16_truncate(d)
+        back = zfpx.f16_restore(h).cpu().numpy().reshape(shape)
+        rep["f16"] = {"bytes_reduction": 2.0,
+                      **{names[f]: {k: float(f"{v:.3e}") for k, v in
+                                    metrics.error_report(x64[f], back[f],
+                                                         pointwise=f in (2, 3)).items()}
+                         for f in range(4)}}
+        rep["float32_storage"] = {
+            names[f]: float(f"{metrics.error_report(x64[f], x32[f], False)['block_mean']:.3e}")
+            for f in range(4)}
+        out[f"T{L}"] = rep
+        del d, x32, x64
     return out
 
 
@@ -726,8 +797,13 @@ def batching_report(torch, zfpx, W, rate=16, reps=10):
     gpu_c, wall_c = timeit(per_chunk)
     nvals = plan.nvalues
     g.close()
+    # compressed-bytes reduction of the buffer (float32 bytes / coded bytes,
+    # partial-block padding included), from the plan's chunk sizes
+    reduction = {f"rate{r}": round(4 * nvals / plan.total_bytes(r), 3) for r in (8, 16, 32)}
+    reduction["f16"] = 2.0
     return {"workload": "lambda->theta buffer, O1280 (2560 rows) x 137 levels f32 (3.617 GB), "
                         "256 chunks of 8 or 12 rows", "rate": rate, "values": nvals,
+            "bytes_reduction": reduction,
             "graph_ms": gpu_g, "direct_ms": gpu_d, "per_chunk_ms": gpu_c,
             "wall_ms": {"graph": wall_g, "direct": wall_d, "per_chunk": wall_c},
             "speedup_graph_vs_per_chunk": round(gpu_c / gpu_g, 3),
@@ -737,8 +813,12 @@ def batching_report(torch, zfpx, W, rate=16, reps=10):
 
 def serving_report(torch, zfpx, W, count):
     """Poisson arrivals of mixed compress/decompress requests (64 KB .. 64 MB of
-    float32, rate 8/16/32) at 25/50/75/90% of the saturated throughput; p50 and
-    p99 latency of the serving loop against one launch per request."""
+    float32, rate 8/16/32): the saturated throughput of the serving loop and
+    of one launch per request (every request at t = 0), then p50/p99 latency
+    of both at 25 .. 125% of the plain form's saturated throughput.  At the
+    100% point every request writes its own output buffer and each served
+    output is compared bit for bit with the same request run alone in one
+    launch (stopping at the first mismatch)."""
     import numpy as np
 
     dev = torch.device("cuda:0")
@@ -752,85 +832,141 @@ def serving_report(torch, zfpx, W, count):
     float_out = [torch.empty_like(pool) for _ in range(nsets)]
     torch.cuda.synchronize()  # inputs complete before the server's own stream reads them
 
-    def build(stream):
-        reqs, nbytes = [], []
+    def out_words(q):
+        return 16 * 2 * (q.nx // 4) * q.rate if q.op == 0 else 8 * 64 * q.nx // 2
+
+    def build(stream, arena=None):
+        reqs, nbytes, outs = [], [], []
+        off = 0
         for i, q in enumerate(stream):
             k = i % nsets
+            if arena is not None:
+                n = out_words(q)
+                o = arena[off: off + n]
+                off += n
             if q.op == 0:
                 view = pool[:, :, : q.nx]
-                rq = zfpx.make_request(0, q.rate, view, words_out[k])
+                o = o if arena is not None else words_out[k]
+                rq = zfpx.make_request(0, q.rate, view, o)
             else:
-                view = float_out[k][:, :, : q.nx]
-                rq = zfpx.make_request(1, q.rate, view, coded[q.rate])
+                o = (o.view(torch.float32).reshape(8, 64, q.nx) if arena is not None
+                     else float_out[k][:, :, : q.nx])
+                rq = zfpx.make_request(1, q.rate, o, coded[q.rate])
             reqs.append(rq)
+            outs.append(o)
             nbytes.append(4 * 8 * 64 * q.nx)
-        return reqs, np.array(nbytes, np.float64)
+        return reqs, np.array(nbytes, np.float64), outs
+
+    def pct(x, p):
+        return round(float(np.percentile(x, p)) * 1e6, 1)
 
     base = W.request_stream(count, 1.0)
-    reqs, nbytes = build(base)
+    reqs, nbytes, _ = build(base)
     zero = np.zeros(count)
-    log(f"serving: saturated throughput ({count} requests at once, one launch each)")
+    log(f"serving: saturated throughput ({count} requests at t = 0), both forms")
     lat = zfpx.zfpx_plain_replay(reqs, zero, timeout_s=60.0)
     sat = nbytes.sum() / lat.max()
+    sv = zfpx.Server(64 << 30, max_slots=1024)
+    try:
+        lat_s = sv.replay(reqs, zero, timeout_s=60.0)
+    finally:
+        sv.close()
+    sat_s = nbytes.sum() / lat_s.max()
     mean_bytes = nbytes.mean()
     out = {"requests_per_point": count, "budget_bytes": 64 << 30,
-           "saturated_gbs_fp32": round(sat / 1e9, 1), "mean_request_mb": round(mean_bytes / 1e6, 2),
-           "note": "request buffers are drawn from 32 rotating sets; latency = completion seen "
-                   "by the host minus scheduled arrival", "points": []}
-    for load in (0.25, 0.5, 0.75, 0.9):
+           "saturated_gbs_fp32": {"server": round(sat_s / 1e9, 1),
+                                  "per_request_launch": round(sat / 1e9, 1)},
+           "mean_request_mb": round(mean_bytes / 1e6, 2),
+           "note": "offered load is a fraction of the per-request-launch form's saturated "
+                   "throughput; request buffers are drawn from 32 rotating sets except at "
+                   "load 1.0, where every request has its own output; latency = completion "
+                   "seen by the host minus scheduled arrival", "points": []}
+    for load in (0.25, 0.5, 0.75, 0.9, 1.0, 1.25):
         gap = mean_bytes / (load * sat)
         stream = W.request_stream(count, gap)
         arrival = np.array([q.t_arrive for q in stream])
-        reqs, nbytes = build(stream)
+        arena = None
+        if load == 1.0:
+            arena = torch.empty(sum(out_words(q) for q in stream), dtype=torch.int64, device=dev)
+        reqs, nbytes, outs = build(stream, arena)
         log(f"serving: load {load:.2f}, mean gap {gap * 1e6:.1f} us")
         sv = zfpx.Server(64 << 30, max_slots=1024)
         try:
             ls = sv.replay(reqs, arrival, timeout_s=60.0)
         finally:
             sv.close()
+        point = {"load": load, "mean_gap_us": round(gap * 1e6, 2)}
+        if arena is not None:
+            torch.cuda.synchronize()
+            checked, first_bad = 0, None
+            for i, (q, o) in enumerate(zip(stream, outs)):
+                if q.op == 0:
+                    ref = zfpx.zfpx_encode_fixed_rate(pool[:, :, : q.nx], q.rate)
+                    same = torch.equal(o, ref)
+                else:
+                    ref = torch.empty((8, 64, q.nx), dtype=torch.float32, device=dev)
+                    zfpx.zfpx_decode_fixed_rate(coded[q.rate], q.rate, ref)
+                    same = torch.equal(o.view(torch.int32), ref.view(torch.int32))
+                if not same:
+                    first_bad = i
+                    break
+                checked += 1
+            point["served_outputs_checked"] = checked
+            point["first_mismatch"] = first_bad
+            del arena, outs
         lp = zfpx.zfpx_plain_replay(reqs, arrival, timeout_s=60.0)
         span_s = (arrival + ls).max()
         span_p = (arrival + lp).max()
-        out["points"].append({
-            "load": load, "mean_gap_us": round(gap * 1e6, 2),
-            "server": {"p50_us": round(float(np.percentile(ls, 50)) * 1e6, 1),
-                       "p99_us": round(float(np.percentile(ls, 99)) * 1e6, 1),
-                       "gbs_fp32": round(nbytes.sum() / span_s / 1e9, 1)},
-            "per_request_launch": {"p50_us": round(float(np.percentile(lp, 50)) * 1e6, 1),
-                                   "p99_us": round(float(np.percentile(lp, 99)) * 1e6, 1),
-                                   "gbs_fp32": round(nbytes.sum() / span_p / 1e9, 1)}})
+        point["server"] = {"p50_us": pct(ls, 50), "p99_us": pct(ls, 99),
+                           "gbs_fp32": round(nbytes.sum() / span_s / 1e9, 1)}
+        point["per_request_launch"] = {"p50_us": pct(lp, 50), "p99_us": pct(lp, 99),
+                                       "gbs_fp32": round(nbytes.sum() / span_p / 1e9, 1)}
+        out["points"].append(point)
+        torch.cuda.empty_cache()
     torch.cuda.synchronize()
     return out
 
 
-def cpu_baseline(cs, rate):
-    """The CPU oracle (plain C, OpenMP over blocks) on the same workload."""
+def cpu_baseline(rate):
+    """The CPU oracle (plain C, OpenMP over blocks) on a bounded sample of the
+    headline workload: the first 8 levels (two 4-level blocks) of the O2560
+    field, every point of each level, pack+encode then decode+unpack at
+    `rate`; the throughput per byte is what the whole 90-level field would
+    see (the time for it is extrapolated linearly)."""
     import numpy as np
 
     import oracle
     from paper_2609_24294_amd import workloads as W
 
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or W.cpu_count()
-    log(f"cpu baseline: oracle on the whole share at rate {rate}, {cores} threads")
-    x32, _ = W.zlambda_fields(want_f64=False)
+    log(f"cpu baseline: oracle on the first 8 levels of the O2560 field at rate {rate}, "
+        f"{cores} threads")
+    x32 = W.large_field_levels(8).reshape(-1)
+    cs = W.reduced_grid_chunkset(n_half=2560, nlev=8, nchunks=1)
+    assert cs.buffer_elems == x32.size
+    cs4 = W.reduced_grid_chunkset(n_half=2560, nlev=4, nchunks=1)
+    x4 = x32[:cs4.buffer_elems]
     oracle.lib()
+    oracle.set_threads(cores)
+    words = oracle.pack_encode(cs4, x4, rate)  # warm-up
     times = []
-    for _ in range(2):
+    back = np.empty(x32.size, np.float32)
+    for _ in range(3):
         t0 = time.perf_counter()
         words = oracle.pack_encode(cs, x32, rate)
         t1 = time.perf_counter()
-        back = np.empty(x32.size, np.float32)
         oracle.decode_unpack(cs, words, rate, back)
         t2 = time.perf_counter()
         times.append((t1 - t0, t2 - t1))
-    te, td = min(times, key=lambda t: t[0] + t[1])
+    te = statistics.median(t[0] for t in times)
+    td = statistics.median(t[1] for t in times)
     nvals = cs.values()
-    # one thread, same work
+    # one thread, the first 4 levels
     oracle.set_threads(1)
     t0 = time.perf_counter()
-    words = oracle.pack_encode(cs, x32, rate)
+    w4 = oracle.pack_encode(cs4, x4, rate)
     t1 = time.perf_counter()
-    oracle.decode_unpack(cs, words, rate, back)
+    oracle.decode_unpack(cs4, w4, rate, back[:x4.size])
     t2 = time.perf_counter()
     oracle.set_threads(cores)
     # numpy's float16 cast and back (the comparator on the host)
@@ -839,13 +975,19 @@ def cpu_baseline(cs, rate):
     t4 = time.perf_counter()
     _ = h.astype(np.float32)
     t5 = time.perf_counter()
+    full = W.LARGE["nlev"] / 8
     return {"value": round(4 * nvals / (te + td) / 1e9, 4), "unit": "GB/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"whole z->lambda share ({nvals} values), pack+encode then decode+unpack "
-                      f"at rate {rate}, best of 2",
+            "sample": f"first 8 of 90 levels of the O2560 field ({nvals} values, "
+                      f"{4 * nvals / 1e9:.3f} GB): pack+encode then decode+unpack at rate {rate}, "
+                      f"median of 3 after a warm-up",
             "encode_s": round(te, 3), "decode_s": round(td, 3),
-            "one_thread": {"encode_s": round(t1 - t0, 3), "decode_s": round(t2 - t1, 3),
-                           "gbs": round(4 * nvals / (t2 - t0) / 1e9, 4)},
+            "encode_gbs": round(4 * nvals / te / 1e9, 4),
+            "decode_gbs": round(4 * nvals / td / 1e9, 4),
+            "whole_field_s_extrapolated": round(full * (te + td), 2),
+            "one_thread": {"sample": "first 4 levels", "encode_s": round(t1 - t0, 3),
+                           "decode_s": round(t2 - t1, 3),
+                           "gbs": round(4 * x4.size / (t2 - t0) / 1e9, 4)},
             "numpy_f16": {"truncate_s": round(t4 - t3, 3), "restore_s": round(t5 - t4, 3),
                           "gbs": round(4 * nvals / (t5 - t3) / 1e9, 4)}}
 

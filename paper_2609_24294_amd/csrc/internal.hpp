@@ -34,6 +34,12 @@ struct RegularDev {
   int32_t nbx, nby;
 };
 
+// 64-block tiles covering n blocks (n up to 2^31 - 1, counted without
+// overflowing 32 bits).
+__host__ __device__ inline int32_t tiles_of(int32_t n) {
+  return (int32_t)(((int64_t)n + 63) >> 6);
+}
+
 // Launch configuration: threads per workgroup and persistent grid (0 = one
 // 64-block tile per wavefront).
 struct LaunchCfg {

@@ -437,7 +437,7 @@ __global__ __launch_bounds__(256) void k_encode(Geo geo, const float* __restrict
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int waves = blockDim.x >> 6;
   uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(rate);
-  const int32_t ntiles = (b_end - b_begin + 63) >> 6;
+  const int32_t ntiles = tiles_of(b_end - b_begin);
   int32_t t = blockIdx.x * waves + wave;
   if (t >= ntiles) return;
   for (;;) {
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int waves = blockDim.x >> 6;
   uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(rate);
-  const int32_t ntiles = (b_end - b_begin + 63) >> 6;
+  const int32_t ntiles = tiles_of(b_end - b_begin);
   int32_t t = blockIdx.x * waves + wave;
   if (t >= ntiles) return;
   for (;;) {
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) void k_encode_var(Geo geo, const float* __rest
   const int waves = blockDim.x >> 6;
   uint64_t* wlds = lds + (size_t)wave * 64 * stride;
   uint64_t* slice = wlds + lane * stride;
-  const int32_t ntiles = (nblocks + 63) >> 6;
+  const int32_t ntiles = tiles_of(nblocks);
   const int32_t t = blockIdx.x * waves + wave;
   if (t >= ntiles) return;
   const int32_t b0 = t << 6;
@@ -646,7 +646,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int waves = blockDim.x >> 6;
   uint64_t* slice = lds + (size_t)(wave * 64 + lane) * stride;
-  const int32_t ntiles = (nblocks + 63) >> 6;
+  const int32_t ntiles = tiles_of(nblocks);
   const int32_t t = blockIdx.x * waves + wave;
   if (t >= ntiles) return;
   const int32_t b0 = t << 6;
@@ -953,18 +953,30 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
 }
 
 // float16 comparator; unaligned buffers take one value per thread.
+// Truncate: groups of 8 values (two 16-byte loads, one 16-byte store); each
+// thread takes four groups a whole grid apart, so eight loads are in flight.
 __global__ __launch_bounds__(256) void k_f16_truncate_v8(const float4* __restrict__ in,
                                                          size_t n8, uint4* __restrict__ out) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8;
-       i += (size_t)gridDim.x * blockDim.x) {
-    float4 a = in[2 * i], b = in[2 * i + 1];
-    auto h = [](float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f); };
-    uint4 r;
-    r.x = h(a.x) | (h(a.y) << 16);
-    r.y = h(a.z) | (h(a.w) << 16);
-    r.z = h(b.x) | (h(b.y) << 16);
-    r.w = h(b.z) | (h(b.w) << 16);
-    out[i] = r;
+  const size_t T = (size_t)gridDim.x * blockDim.x;
+  auto h = [](float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f); };
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8; i += 4 * T) {
+    float4 a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (i + k * T < n8) {
+        a[k] = in[2 * (i + k * T)];
+        b[k] = in[2 * (i + k * T) + 1];
+      }
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+      if (i + k * T < n8) {
+        uint4 r;
+        r.x = h(a[k].x) | (h(a[k].y) << 16);
+        r.y = h(a[k].z) | (h(a[k].w) << 16);
+        r.z = h(b[k].x) | (h(b[k].y) << 16);
+        r.w = h(b[k].z) | (h(b[k].w) << 16);
+        out[i + k * T] = r;
+      }
   }
 }
 
@@ -1150,7 +1162,7 @@ hipError_t launch_f16_truncate(const float* in, size_t n, uint16_t* out, hipStre
   size_t done = 0;
   if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0 && n >= 8) {
     size_t n8 = n / 8;
-    hipLaunchKernelGGL(k_f16_truncate_v8, dim3(elementwise_grid(n8)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_f16_truncate_v8, dim3(elementwise_grid((n8 + 3) / 4)), dim3(256), 0, s,
                        reinterpret_cast<const float4*>(in), n8, reinterpret_cast<uint4*>(out));
     done = n8 * 8;
   }
@@ -1208,7 +1220,7 @@ hipError_t launch_plan_encode_var(const PlanDev& p, bool vec4, const float* src,
                                   int32_t nblocks, int maxprec, int minexp, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   constexpr int wg = 128;
-  const int ntiles = (nblocks + 63) >> 6;
+  const int ntiles = tiles_of(nblocks);
   dim3 grid((ntiles + wg / 64 - 1) / (wg / 64)), block(wg);
   size_t shm = lds_bytes(wg, cap);
   PlanGeo geo{p};
@@ -1235,7 +1247,7 @@ hipError_t launch_plan_decode_var(const PlanDev& p, bool vec4, const uint32_t* i
                                   hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   constexpr int wg = 128;
-  const int ntiles = (nblocks + 63) >> 6;
+  const int ntiles = tiles_of(nblocks);
   dim3 grid((ntiles + wg / 64 - 1) / (wg / 64)), block(wg);
   size_t shm = lds_bytes(wg, cap);
   PlanGeo geo{p};

@@ -6,7 +6,7 @@ import torch
 import oracle
 from paper_2609_24294_amd import workloads as W
 
-from _blocks import array_to_blocks, block_families, blocks_to_array
+from _blocks import array_to_blocks, block_families, blocks_to_array, real_values
 
 pytestmark = pytest.mark.gpu
 
@@ -111,6 +111,7 @@ def _check_plan(zfpx_lib, cs, src, rates, full=True, sample=0, seed=0):
             want = oracle.pack_encode_sample(cs, src, rate, ids)
             assert np.array_equal(got.reshape(-1, rate)[ids], want), rate
             vals, pos, inside = oracle.decode_sample(cs, got, rate, ids)
+            assert int(inside.sum()) == int(real_values(cs, ids).sum()), rate
             dh = dst.cpu().numpy()
             assert np.array_equal(f32bits(dh[pos[inside]]), f32bits(vals[inside])), rate
     return plan
@@ -142,31 +143,41 @@ def test_ragged_plans_small(zfpx_lib):
 def test_per_chunk_launches_equal_one_launch(zfpx_lib):
     cs = W.reduced_grid_chunkset(n_half=48, nlev=9, nchunks=12)
     rng = np.random.default_rng(6)
-    src = torch.from_numpy(rng.standard_normal(cs.buffer_elems).astype(np.float32)).to(DEV)
+    host = rng.standard_normal(cs.buffer_elems).astype(np.float32)
+    src = torch.from_numpy(host).to(DEV)
     plan = zfpx_lib.Plan.from_chunkset(cs)
     for rate in (8, 16):
+        want = oracle.pack_encode(cs, host, rate)
+        back = np.zeros(cs.buffer_elems, np.float32)
+        oracle.decode_unpack(cs, want, rate, back)
         whole = zfpx_lib.zfpx_pack_encode(plan, src, rate)
+        assert np.array_equal(u64(whole), want), rate
         parts = torch.zeros_like(whole)
         for c in range(cs.nchunks):
             zfpx_lib.zfpx_pack_encode_chunks(plan, c, 1, src, rate, parts)
-        assert torch.equal(whole, parts)
+        assert np.array_equal(u64(parts), want), rate
         d1 = torch.zeros_like(src)
         d2 = torch.zeros_like(src)
         zfpx_lib.zfpx_decode_unpack(plan, whole, rate, d1)
         for c in range(cs.nchunks):
             zfpx_lib.zfpx_decode_unpack_chunks(plan, c, 1, whole, rate, d2)
-        assert torch.equal(d1, d2)
+        assert np.array_equal(f32bits(d1.cpu().numpy()), f32bits(back)), rate
+        assert np.array_equal(f32bits(d2.cpu().numpy()), f32bits(back)), rate
 
 
 def test_every_launch_config_gives_identical_bytes(zfpx_lib):
     cs = W.reduced_grid_chunkset(n_half=64, nlev=11, nchunks=16)
     rng = np.random.default_rng(7)
-    src = torch.from_numpy((280 + 15 * rng.standard_normal(cs.buffer_elems)).astype(np.float32)).to(DEV)
+    host = (280 + 15 * rng.standard_normal(cs.buffer_elems)).astype(np.float32)
+    src = torch.from_numpy(host).to(DEV)
     plan = zfpx_lib.Plan.from_chunkset(cs)
     for rate in (8, 32):
-        ref = zfpx_lib.zfpx_pack_encode(plan, src, rate)
-        dref = torch.zeros_like(src)
-        zfpx_lib.zfpx_decode_unpack(plan, ref, rate, dref)
+        # the reference is the oracle's stream and decode, moved to the device
+        want = oracle.pack_encode(cs, host, rate)
+        back = np.zeros(cs.buffer_elems, np.float32)
+        oracle.decode_unpack(cs, want, rate, back)
+        ref = torch.from_numpy(want.view(np.int64)).to(DEV)
+        dref = torch.from_numpy(back).to(DEV)
         for wg in (64, 128, 256):
             for grid in (0, 1, 3, 64):
                 for op in (0, 1):
@@ -178,7 +189,15 @@ def test_every_launch_config_gives_identical_bytes(zfpx_lib):
                 d = torch.zeros_like(src)
                 zfpx_lib.zfpx_decode_unpack(plan, w, rate, d)
                 assert torch.equal(w, ref), (wg, grid)
-                assert torch.equal(d, dref), (wg, grid)
+                assert torch.equal(d.view(torch.int32), dref.view(torch.int32)), (wg, grid)
+        # and the configuration the autotuner picks
+        for op in (0, 1):
+            zfpx_lib.zfpx_autotune(plan, op, rate, src, torch.empty_like(ref), torch.empty_like(src))
+        w = zfpx_lib.zfpx_pack_encode(plan, src, rate)
+        d = torch.zeros_like(src)
+        zfpx_lib.zfpx_decode_unpack(plan, w, rate, d)
+        assert torch.equal(w, ref), "autotuned"
+        assert torch.equal(d.view(torch.int32), dref.view(torch.int32)), "autotuned"
 
 
 def test_graph_replays_match_eager(zfpx_lib):
@@ -188,9 +207,11 @@ def test_graph_replays_match_eager(zfpx_lib):
     src = torch.from_numpy(host).to(DEV)
     plan = zfpx_lib.Plan.from_chunkset(cs)
     rate = 16
-    send_e = zfpx_lib.zfpx_pack_encode(plan, src, rate)
-    dst_e = torch.zeros_like(src)
-    zfpx_lib.zfpx_decode_unpack(plan, send_e, rate, dst_e)
+    want = oracle.pack_encode(cs, host, rate)
+    back = np.zeros(cs.buffer_elems, np.float32)
+    oracle.decode_unpack(cs, want, rate, back)
+    send_e = torch.from_numpy(want.view(np.int64)).to(DEV)
+    dst_e = torch.from_numpy(back).to(DEV)
     send = torch.zeros_like(send_e)
     dst = torch.zeros_like(src)
     g = zfpx_lib.Graph(plan, rate, src, send, dst)
@@ -247,21 +268,104 @@ def test_empty_inputs(zfpx_lib):
     assert send.numel() == 0
 
 
-def test_large_full_size_sampled(zfpx_lib):
-    """O2560 x 90 levels (9.47 GB, one chunk, 37,859,840 blocks): full-size
-    launches, sampled blocks against the oracle.  Levels 8..89 repeat 0..7."""
+def _full_parity(zfpx_lib, cs, host, dsrc, plan, rate):
+    """Whole-buffer stream and decode of the default launch against the
+    oracle; returns the device stream and decode for further comparisons."""
+    send = zfpx_lib.zfpx_pack_encode(plan, dsrc, rate)
+    dst = torch.full_like(dsrc, float("nan"))
+    zfpx_lib.zfpx_decode_unpack(plan, send, rate, dst)
+    torch.cuda.synchronize()
+    want = oracle.pack_encode(cs, host, rate)
+    got = u64(send)
+    bad = np.nonzero((got != want).reshape(-1, rate).any(1))[0]
+    assert bad.size == 0, f"rate {rate}: {bad.size} blocks differ, first {bad[:5]}"
+    del got
+    back = np.full(host.size, np.nan, np.float32)
+    oracle.decode_unpack(cs, want, rate, back)
+    del want
+    dh = dst.cpu().numpy()
+    diff = np.nonzero(f32bits(dh) != f32bits(back))[0]
+    assert diff.size == 0, f"rate {rate}: {diff.size} values differ, first {diff[:5]}"
+    return send, dst
+
+
+@pytest.fixture(scope="module")
+def large_buffer(zfpx_lib):
+    """O2560 x 90 levels (9.47 GB, one chunk, 37,859,840 blocks); levels
+    8..89 repeat the generated levels 0..7."""
     cs = W.large_chunkset()
-    x32 = W.large_field_repeated(W.large_field_levels(8))
-    assert x32.size == cs.buffer_elems == 2367590400
-    plan = _check_plan(zfpx_lib, cs, x32, (8, 16), full=False, sample=2000, seed=13)
+    host = W.large_field_repeated(W.large_field_levels(8)).reshape(-1)
+    assert host.size == cs.buffer_elems == 2367590400
+    plan = zfpx_lib.Plan.from_chunkset(cs)
     assert plan.nblocks == 37859840
-    _, _, total = plan.sizes(8)
-    assert total == 37859840 * 64
+    dsrc = torch.from_numpy(host).to(DEV)
+    yield cs, host, dsrc, plan
+    del dsrc
+    torch.cuda.empty_cache()
 
 
-def test_ltheta_full_size_sampled(zfpx_lib):
+@pytest.mark.parametrize("rate", [8, 16])
+def test_large_full_buffer_parity(zfpx_lib, large_buffer, rate):
+    """Every block of the O2560 x 90 buffer, streams and decoded floats, in
+    the launch configuration the benchmark times."""
+    cs, host, dsrc, plan = large_buffer
+    _, _, total = plan.sizes(rate)
+    assert total == 37859840 * 8 * rate
+    send, dst = _full_parity(zfpx_lib, cs, host, dsrc, plan, rate)
+    del send, dst
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def ltheta_buffer(zfpx_lib):
     cs = W.ltheta_chunkset()
-    x32 = W.ltheta_field()
-    plan = _check_plan(zfpx_lib, cs, x32, (8, 16), full=False, sample=3000, seed=11)
-    b, o, total = plan.sizes(16)
-    assert b.size == 256 and total == 14470400 * 128
+    host = W.ltheta_field().reshape(-1)
+    plan = zfpx_lib.Plan.from_chunkset(cs)
+    dsrc = torch.from_numpy(host).to(DEV)
+    yield cs, host, dsrc, plan
+    del dsrc
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("rate", [8, 16, 32])
+def test_ltheta_full_buffer_parity(zfpx_lib, ltheta_buffer, rate):
+    """The O1280 x 137 lambda->theta buffer (256 uneven chunks, 3.617 GB),
+    every block against the oracle; at rate 16 also the forms the benchmark
+    compares: autotuned launches captured in a graph, and one launch per
+    chunk."""
+    cs, host, dsrc, plan = ltheta_buffer
+    b, o, total = plan.sizes(rate)
+    assert b.size == 256 and total == 14470400 * 8 * rate
+    send, dst = _full_parity(zfpx_lib, cs, host, dsrc, plan, rate)
+    if rate == 16:
+        s2 = torch.empty_like(send)
+        d2 = torch.empty_like(dst)
+        for op in (0, 1):
+            zfpx_lib.zfpx_autotune(plan, op, rate, dsrc, s2, d2)
+        s2.zero_()
+        d2.fill_(-1.0)
+        g = zfpx_lib.Graph(plan, rate, dsrc, s2, d2)
+        for rep in range(2):
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(s2, send), ("graph", rep)
+            assert torch.equal(d2.view(torch.int32), dst.view(torch.int32)), ("graph", rep)
+            s2.zero_()
+            d2.fill_(-1.0)
+        g.close()
+        for c in range(cs.nchunks):
+            zfpx_lib.zfpx_pack_encode_chunks(plan, c, 1, dsrc, rate, s2)
+        for c in range(cs.nchunks):
+            zfpx_lib.zfpx_decode_unpack_chunks(plan, c, 1, s2, rate, d2)
+        torch.cuda.synchronize()
+        assert torch.equal(s2, send), "per-chunk launches"
+        assert torch.equal(d2.view(torch.int32), dst.view(torch.int32)), "per-chunk launches"
+        # sampled blocks through the sampling helpers, with their in-range counts
+        rng = np.random.default_rng(11)
+        ids = np.unique(np.concatenate([rng.integers(0, plan.nblocks, 2000),
+                                        [0, plan.nblocks - 1]]))
+        vals, pos, inside = oracle.decode_sample(cs, u64(send), rate, ids)
+        assert int(inside.sum()) == int(real_values(cs, ids).sum())
+        del s2, d2
+    del send, dst
+    torch.cuda.empty_cache()

@@ -1,11 +1,13 @@
-"""Serving loop: every result in the mix equals the request run alone
-(tolerance 0), admission respects the HBM budget, errors are reported."""
+"""Serving loop: every result in the mix equals the request run alone and
+the CPU oracle's result for the same view (tolerance 0), admission respects
+the HBM budget, errors are reported."""
 import time
 
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2609_24294_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -13,9 +15,25 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
+def _oracle_ref(op, rate, view, words=None):
+    """The oracle's output for a request: the stream of the host copy of the
+    float32 view (op 0), or the decode of the request's input stream (op 1)."""
+    if op == 0:
+        host = view.contiguous().cpu().numpy()
+        return torch.from_numpy(oracle.encode_regular(host, rate).view(np.int64)).to(DEV)
+    w = words.cpu().numpy().view(np.uint64)
+    return torch.from_numpy(oracle.decode_regular(w, tuple(view.shape), rate)).to(DEV)
+
+
+def _same(a, b):
+    return torch.equal(a.view(torch.int32) if a.dtype == torch.float32 else a,
+                       b.view(torch.int32) if b.dtype == torch.float32 else b)
+
+
 def _requests(zfpx, pool, rng, count):
     """Mixed encode/decode requests on views of `pool`, each with its own
-    output buffer, plus the expected outputs computed one launch at a time."""
+    output buffer, plus the expected outputs: the oracle's, which the same
+    request run alone in one launch reproduces."""
     reqs, outs, refs = [], [], []
     for i in range(count):
         op = int(rng.integers(0, 2))
@@ -27,14 +45,17 @@ def _requests(zfpx, pool, rng, count):
         nbytes = zfpx.zfpx_fixed_rate_bytes(view.shape[2], view.shape[1], view.shape[0], rate)
         if op == 0:
             words = torch.zeros(nbytes // 8, dtype=torch.int64, device=DEV)
-            ref = zfpx.zfpx_encode_fixed_rate(view, rate)
+            ref = _oracle_ref(0, rate, view)
+            assert _same(zfpx.zfpx_encode_fixed_rate(view, rate), ref), (i, "alone")
             reqs.append(zfpx.make_request(0, rate, view, words, tag=i))
             outs.append(words)
         else:
             src_words = zfpx.zfpx_encode_fixed_rate(view, rate)
             arr = torch.full(view.shape, -7.0, device=DEV)
-            ref = torch.full(view.shape, -7.0, device=DEV)
-            zfpx.zfpx_decode_fixed_rate(src_words, rate, ref)
+            ref = _oracle_ref(1, rate, view, src_words)
+            alone = torch.full(view.shape, -7.0, device=DEV)
+            zfpx.zfpx_decode_fixed_rate(src_words, rate, alone)
+            assert _same(alone, ref), (i, "alone")
             reqs.append(zfpx.make_request(1, rate, arr, src_words, tag=i))
             outs.append((arr, src_words))
         refs.append(ref)
@@ -45,7 +66,7 @@ def _requests(zfpx, pool, rng, count):
 def _check(outs, refs):
     for i, (o, r) in enumerate(zip(outs, refs)):
         got = o if isinstance(o, torch.Tensor) else o[0]
-        assert torch.equal(got, r), f"request {i} differs from its one-launch result"
+        assert _same(got, r), f"request {i} differs from the oracle and its one-launch result"
 
 
 def test_server_mix_equals_alone(zfpx_lib):
@@ -133,7 +154,8 @@ def test_server_large_requests_in_runs(zfpx_lib):
     for i, nx in enumerate([32764, 12, 16384, 300, 32768, 4, 20001, 64]):
         view = pool[:, :, :nx]
         rate = int(rng.choice([8, 16, 32]))
-        words = zfpx_lib.zfpx_encode_fixed_rate(view, rate)
+        words = _oracle_ref(0, rate, view)
+        assert _same(zfpx_lib.zfpx_encode_fixed_rate(view, rate), words), (i, "alone")
         if i % 2 == 0:
             out = torch.zeros_like(words)
             reqs.append(zfpx_lib.make_request(0, rate, view, out, tag=i))
@@ -141,16 +163,14 @@ def test_server_large_requests_in_runs(zfpx_lib):
             refs.append(words)
         else:
             arr = torch.full(view.shape, -7.0, device=DEV)
-            ref = torch.full(view.shape, -7.0, device=DEV)
-            zfpx_lib.zfpx_decode_fixed_rate(words, rate, ref)
+            ref = _oracle_ref(1, rate, view, words)
             reqs.append(zfpx_lib.make_request(1, rate, arr, words, tag=i))
             outs.append((arr, words))  # requests hold raw pointers: keep inputs alive
             refs.append(ref)
         # decoding the large ones too (runs on the decode path)
         if nx >= 16384:
             arr = torch.full(view.shape, -7.0, device=DEV)
-            ref = torch.full(view.shape, -7.0, device=DEV)
-            zfpx_lib.zfpx_decode_fixed_rate(words, rate, ref)
+            ref = _oracle_ref(1, rate, view, words)
             reqs.append(zfpx_lib.make_request(1, rate, arr, words, tag=100 + i))
             outs.append((arr, words))
             refs.append(ref)
@@ -177,9 +197,9 @@ def test_server_array_beyond_4gib(zfpx_lib):
     base[sz: sz + ny * nx] = lev[1].reshape(-1)
     view = torch.as_strided(base, (2, ny, nx), (sz, nx, 1))
     rate = 16
-    words = zfpx_lib.zfpx_encode_fixed_rate(view, rate)
-    ref = torch.full((2, ny, nx), -7.0, device=DEV)
-    zfpx_lib.zfpx_decode_fixed_rate(words, rate, ref)
+    words = _oracle_ref(0, rate, view)
+    assert _same(zfpx_lib.zfpx_encode_fixed_rate(view, rate), words)
+    ref = _oracle_ref(1, rate, view, words)
     out_words = torch.zeros_like(words)
     out_view = torch.as_strided(base, (2, ny, nx), (sz, nx, 1))
     sv = zfpx_lib.Server(64 << 30, max_slots=4)
@@ -193,4 +213,4 @@ def test_server_array_beyond_4gib(zfpx_lib):
     torch.cuda.synchronize()
     assert torch.equal(out_words, words)
     got = torch.stack([base[:ny * nx].reshape(ny, nx), base[sz: sz + ny * nx].reshape(ny, nx)])
-    assert torch.equal(got, ref)
+    assert _same(got, ref)
