@@ -98,6 +98,9 @@ ZFPX_HD uint64_t low_mask(int n) {  // n in [0, 64]
   return n >= 64 ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
 }
 
+// low_mask(n) for n in [1, 64] without a select: 2 << 63 wraps to 0.
+ZFPX_HD uint64_t mask_upto(int n) { return ((uint64_t)2 << (n - 1)) - 1; }
+
 ZFPX_HD int ctz64(uint64_t x) {  // x != 0
   return __builtin_ctzll(x);
 }
@@ -359,14 +362,15 @@ ZFPX_HD uint32_t encode_block(float* v, uint64_t* out, int rate_rt, int maxprec 
   transpose32x2<true>(X);
   uint32_t pos = 9;
   int n = 0;
+  uint64_t vm = 0;  // low_mask(n), updated only when n changes
 #pragma unroll
   for (int k = 31; k >= 0; k--) {
     if (pos < maxbits && k >= kmin) {
-      uint64_t x = X[k];
-      uint64_t y = n < 64 ? (x >> n) : 0;  // bits not yet significant
-      or_bits(out, pos, x & low_mask(n));  // the first n bits verbatim
+      const uint64_t x = X[k];
+      or_bits(out, pos, x & vm);  // the first n bits verbatim
       pos += n;
-      if (y != 0 && pos < maxbits) {
+      if ((x & ~vm) != 0 && pos < maxbits) {
+        uint64_t y = x >> n;  // bits not yet significant (n < 64 here)
         // Each newly significant coefficient costs a group test 1, the zeros
         // up to it and its own 1 (that one is implied, and not written, for
         // coefficient 63).  Common case: all of the plane's groups fit one
@@ -399,6 +403,7 @@ ZFPX_HD uint32_t encode_block(float* v, uint64_t* out, int rate_rt, int maxprec 
           n += p + 1;
           y = (y >> p) >> 1;
         }
+        vm = mask_upto(n);
       }
       pos += n < 64 ? 1 : 0;  // group test 0 (a zero bit)
     }
@@ -410,15 +415,57 @@ ZFPX_HD uint32_t encode_block(float* v, uint64_t* out, int rate_rt, int maxprec 
 // Decoder
 // ---------------------------------------------------------------------------
 
+// Population count of a 64-bit word.
+ZFPX_HD int popc64(uint64_t x) { return __builtin_popcountll(x); }
+
+// The group tests and scans that follow a group test of 1, parsed from the
+// 64 stream bits v after it (bit 0 first), without a loop over the groups.
+// Each group is zeros up to a one (the newly significant coefficient), and
+// the group test after it is 1 if another group follows: so inside every
+// maximal run of ones that starts right after a zero (or at bit 0) the bits
+// alternate coefficient-one, group-test, coefficient-one, ...; a run that
+// ends on a coefficient-one is followed by the closing group test 0.
+// Returns the window position p of that last coefficient-one (64 if the
+// window holds none) and, through ev, the coefficient-ones at positions
+// 0..p.
+ZFPX_HD int parse_groups(uint64_t v, uint64_t& ev) {
+  constexpr uint64_t kEven = 0x5555555555555555ull;
+  const uint64_t starts = v & ~(v << 1);
+  // runs that start at an even position turn to zeros when their start bit
+  // is added (the carry runs through them); the others are unchanged
+  const uint64_t t = v + (starts & kEven);
+  // coefficient-ones: even positions of even-started runs, odd positions of
+  // odd-started runs
+  const uint64_t e = v & (t ^ kEven);
+  const uint64_t ends = e & ~(v >> 1);
+  if (ends == 0) {
+    ev = 0;
+    return 64;
+  }
+  const int p = ctz64(ends);
+  ev = e & (((uint64_t)2 << p) - 1);  // p <= 63: 2 << 63 wraps to 0, mask all ones
+  return p;
+}
+
 // Decode the slice `in` (rate words followed by kSlackWords zero words) into
 // 64 floats (block-local order).
+//
+// Stream positions never pass maxbits (reads there return the zero slack,
+// which is what a budget that has run out yields for verbatim bits and group
+// tests).  Per bit plane: the verbatim bits are the window at pos masked to
+// the n significant coefficients, and the group test is bit n of the same
+// window; a plane whose group test is 0 (most of them) is done with that.
+// Otherwise the groups are parsed from the window after the group test
+// (parse_groups), unless the budget ends inside them or a scan could reach
+// coefficient 63 (whose one is implied, not coded): those take the
+// group-by-group loop.
 template <int RATE>
 ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxprec = 32,
                           int minexp = kMinExpNone) {
   const int rate = RATE > 0 ? RATE : rate_rt;
   const uint32_t maxbits = 64u * (uint32_t)rate;
-  // The header (bits 0..8) and, in the same three words, both windows of
-  // the first plane (n = 0, so they start at bit 9): one round trip.
+  // the header (bits 0..8) and the first plane's window (from bit 9) are in
+  // the first three words: one round trip
   Words3 wfirst = window_words(in, 0);
   pin_words(wfirst);
   const uint32_t head = wfirst.w0;
@@ -431,78 +478,58 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
   }
   uint64_t X[32];  // bit planes, then (after the transpose) coefficients s, 32+s
   int n = 0;
+  uint64_t vm = 0;  // low_mask(n)
 #pragma unroll
   for (int k = 31; k >= 0; k--) {
     uint64_t x = 0;
-    if (pos < maxbits && k >= kmin) {
-      int m = (int)(maxbits - pos) < n ? (int)(maxbits - pos) : n;
-      // Both windows of the plane in one round trip: the verbatim bits at
-      // pos and the group tests after them (pos + m <= maxbits, so both stay
-      // inside the slice).  Left to itself the compiler waits for the first
-      // window before reading the second, and moves part of the second
-      // behind a branch: three dependent round trips per plane.
-      Words3 wv = wfirst, ws = wfirst;
-      if (k < 31) {
-        wv = window_words(in, pos);
-        ws = window_words(in, pos + m);
-        pin_words(wv, ws);
-      }
-      uint64_t s = window_of(ws, pos + m);  // group tests and scans
-      x = window_of(wv, pos) & low_mask(m);  // the first n bits verbatim
-      pos += m;
-      if (n < 64 && pos < maxbits) {
-        // Common case first: every group test and scan of the plane lies in
-        // one 64-bit window, inside the budget, and no scan reaches
-        // coefficient 63 (whose one would be implied).  Otherwise the plane
-        // is decoded group by group from the same state.
-        bool done = false;
-        uint64_t y = 0;
-        int c = 0, used = 1;  // coefficients and bits taken; the closing zero
-        while (s & 1) {
-          uint64_t r = s >> 1;  // bit 63 clear
-          // with bit 63 set, t = 63 means no one was left in the window: the
-          // window test below then fails (used > 64), and s becomes 0
-          int t = ctz64(r | (uint64_t(1) << 63));
-          y |= uint64_t(1) << ((c + t) & 63);
-          c += t + 1;
-          used += t + 2;
-          s = (r >> t) >> 1;
-        }
-        if (used <= 64 && pos + used <= maxbits && n + c <= 63) {
+    if (k >= kmin && pos < maxbits) {
+      const uint64_t w = k == 31 ? window_of(wfirst, pos) : window64(in, pos);
+      x = w & vm;  // verbatim bits (zeros past the budget)
+      const uint32_t gpos = pos + (uint32_t)n;
+      const bool group = n < 64 && ((w >> (n & 63)) & 1) && gpos < maxbits;
+      pos = gpos + (n < 64 ? 1u : 0u);
+      if (group) {
+        // pos is the bit after the group test of 1
+        uint64_t ev;
+        const int p = parse_groups(window64(in, pos), ev);
+        const int m = popc64(ev);
+        const int last = n + p + 1 - m;  // coefficient of the last one found
+        if (p < 63 && pos + (uint32_t)p < maxbits && last <= 62) {
+          // each coefficient-one moves down by the number of group tests
+          // before it: y = ev - sum_t (ev without its lowest t ones) >> t
+          uint64_t y = ev, e = ev;
+          for (int t = 1;; t++) {
+            e &= e - 1;
+            if (e == 0) break;
+            y -= e >> t;
+          }
           x |= y << n;
-          n += c;
-          pos += used;
-          done = true;
-        }
-        if (!done) {
-          uint64_t w = window64(in, pos);
-          int g = (int)(w & 1);  // first group test
-          pos += 1;
-          w >>= 1;
-          int avail = 63;
+          n = last + 1;
+          pos += (uint32_t)p + 2;  // through the closing group test 0
+        } else {
+          // group by group from the first scan: zeros up to the next one,
+          // at most up to coefficient 63 (implied) or the end of the budget
+          int g = 1;
           while (g) {
-            // scan: zeros up to the next one, at most lim positions
             int lim = 63 - n;
             if ((int)(maxbits - pos) < lim) lim = (int)(maxbits - pos);
-            // the scan and the next group test need up to lim + 2 bits
-            if (avail < lim + 2 && (w == 0 || ctz64(w) + 2 > avail)) {
-              w = window64(in, pos);
-              avail = 64;
-            }
-            int z = w ? ctz64(w) : 64;
-            int t = z < lim ? z : lim;
-            int found = z < lim;
+            const uint64_t s = window64(in, pos);
+            const int z = s ? ctz64(s) : 64;
+            const int t = z < lim ? z : lim;
+            const int found = z < lim;
             x |= uint64_t(1) << (n + t);
             n += t + 1;
-            pos += t + found;
-            int u = t + found;  // <= 63
-            g = (n < 64 && pos < maxbits) ? (int)((w >> u) & 1) : 0;
-            pos += n < 64 ? 1 : 0;
-            w = (w >> u) >> 1;
-            avail -= u + 1;
+            pos += (uint32_t)(t + found);
+            g = 0;
+            if (n < 64 && pos < maxbits) {
+              g = (int)((s >> (t + found)) & 1);  // t + found <= 63
+              pos += 1;
+            }
           }
         }
+        vm = mask_upto(n);  // n >= 1 after a group test of 1
       }
+      if (pos > maxbits) pos = maxbits;
     }
     X[k] = x;
   }

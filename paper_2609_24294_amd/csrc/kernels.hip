@@ -39,8 +39,38 @@ __device__ __forceinline__ T uniform_load(const T* p, int64_t i) {
   return ((const __attribute__((address_space(4))) T*)p)[i];
 }
 
+// A tile whose 64 blocks all lie in one run: everything but the x offset is
+// wave-uniform (scalar registers), so whole blocks load through a scalar row
+// base plus a per-lane offset.
+struct RunView {
+  int64_t rbase[4];
+  int64_t lstride;
+  int32_t nlev, nrow, block0;
+  int32_t minlen;  // shortest row of the group
+  int32_t rlen[4];
+};
+
 struct PlanGeo {
   PlanDev p;
+  // True (the same on every lane) when blocks b0 .. b0 + nact - 1 lie in one
+  // run; r then describes it.
+  __device__ __forceinline__ bool one_run(int32_t b0, int nact, RunView& r) const {
+    int32_t s = uniform_load(p.tile_seg, b0 >> 6);
+    while (uniform_load(p.seg_block0, s + 1) <= b0) s++;
+    if (uniform_load(p.seg_block0, s + 1) <= b0 + nact - 1) return false;
+    const SegDesc* d = p.segs + s;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      r.rbase[i] = uniform_load(&d->rbase[i], 0);
+      r.rlen[i] = uniform_load(&d->rlen[i], 0);
+    }
+    r.lstride = uniform_load(&d->lstride, 0);
+    r.nlev = uniform_load(&d->nlev, 0);
+    r.nrow = uniform_load(&d->nrow, 0);
+    r.block0 = uniform_load(&d->block0, 0);
+    r.minlen = min(min(r.rlen[0], r.rlen[1]), min(r.rlen[2], r.rlen[3]));
+    return true;
+  }
   // Any block: find its run from the run table.
   __device__ __forceinline__ void locate(int32_t b, BlockView& v) const {
     int32_t s = p.tile_seg[b >> 6];
@@ -121,6 +151,7 @@ struct RegularGeo {
   __device__ __forceinline__ void locate_tile(int32_t b0, int lane, int, BlockView& v) const {
     locate(b0 + lane, v);
   }
+  __device__ __forceinline__ bool one_run(int32_t, int, RunView&) const { return false; }
 };
 
 // COH: system-coherent element accesses that bypass the (per-XCD) L2, used by
@@ -267,6 +298,74 @@ __device__ __forceinline__ void scatter(float* __restrict__ dst, const BlockView
   }
 }
 
+// Block b of a one-run tile: whole blocks load sixteen 16-byte pieces at a
+// scalar row address plus the lane's x offset; others take the clamped
+// element path of gather().
+template <bool VEC4>
+__device__ __forceinline__ void gather_run(const float* __restrict__ src, const RunView& r,
+                                           int32_t b, float* val) {
+  const int32_t x0 = 4 * (b - r.block0);
+  if (VEC4 && r.nlev == 4 && r.nrow == 4 && x0 + 3 < r.minlen) {
+#pragma unroll
+    for (int dz = 0; dz < 4; dz++) {
+#pragma unroll
+      for (int dy = 0; dy < 4; dy++) {
+        const float* row = src + (r.rbase[dy] + dz * r.lstride);
+        f32x4 f = *reinterpret_cast<const f32x4*>(row + (uint32_t)x0);
+        float* o = val + 16 * dz + 4 * dy;
+        o[0] = f.x;
+        o[1] = f.y;
+        o[2] = f.z;
+        o[3] = f.w;
+      }
+    }
+    return;
+  }
+  BlockView v;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    v.rbase[i] = r.rbase[i];
+    v.rlen[i] = r.rlen[i];
+  }
+  v.lstride = r.lstride;
+  v.sx = 1;
+  v.nlev = r.nlev;
+  v.nrow = r.nrow;
+  v.x0 = x0;
+  gather<false>(src, v, val);
+}
+
+template <bool VEC4>
+__device__ __forceinline__ void scatter_run(float* __restrict__ dst, const RunView& r, int32_t b,
+                                            const float* val) {
+  const int32_t x0 = 4 * (b - r.block0);
+  if (VEC4 && r.nlev == 4 && r.nrow == 4 && x0 + 3 < r.minlen) {
+#pragma unroll
+    for (int dz = 0; dz < 4; dz++) {
+#pragma unroll
+      for (int dy = 0; dy < 4; dy++) {
+        float* row = dst + (r.rbase[dy] + dz * r.lstride);
+        const float* o = val + 16 * dz + 4 * dy;
+        f32x4 f = {o[0], o[1], o[2], o[3]};
+        *reinterpret_cast<f32x4*>(row + (uint32_t)x0) = f;
+      }
+    }
+    return;
+  }
+  BlockView v;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    v.rbase[i] = r.rbase[i];
+    v.rlen[i] = r.rlen[i];
+  }
+  v.lstride = r.lstride;
+  v.sx = 1;
+  v.nlev = r.nlev;
+  v.nrow = r.nrow;
+  v.x0 = x0;
+  scatter<VEC4>(dst, v, val);
+}
+
 // Make loaded values available at this point (an empty asm that reads and
 // writes them): the loads are then all issued before the first wait, instead
 // of one round trip each behind the guards of their uses.
@@ -395,11 +494,17 @@ __device__ __forceinline__ void encode_tile(const Geo& geo, const float* __restr
   const int stride = lds_stride(RATE > 0 ? RATE : rate);
   uint64_t* slice = wlds + lane * stride;
   for (int i = 0; i < stride; i++) slice[i] = 0;
+  RunView run;
+  const bool uniform = !COH && geo.one_run(b0, nact, run);
   if (lane < nact) {
-    BlockView v;
-    geo.locate_tile(b0, lane, nact, v);
     float val[64];
-    gather<VEC4, COH>(src, v, val, vspan);
+    if (uniform) {
+      gather_run<VEC4>(src, run, b0 + lane, val);
+    } else {
+      BlockView v;
+      geo.locate_tile(b0, lane, nact, v);
+      gather<VEC4, COH>(src, v, val, vspan);
+    }
     encode_block<RATE>(val, slice, rate);
   }
   wave_sync_lds();
@@ -419,9 +524,14 @@ __device__ __forceinline__ void decode_tile(const Geo& geo, const uint64_t* __re
   if (lane < nact) {
     float val[64];
     decode_block<RATE>(wlds + opaque(lane) * stride, val, rate);
-    BlockView v;
-    geo.locate_tile(b0, lane, nact, v);
-    scatter<VEC4, COH>(dst, v, val, vspan);
+    RunView run;
+    if (!COH && geo.one_run(b0, nact, run)) {
+      scatter_run<VEC4>(dst, run, b0 + lane, val);
+    } else {
+      BlockView v;
+      geo.locate_tile(b0, lane, nact, v);
+      scatter<VEC4, COH>(dst, v, val, vspan);
+    }
   }
 }
 
