@@ -285,6 +285,29 @@ int zfpx_plan_encode_var(const zfpx_plan* plan, const float* d_src, int64_t src_
                          size_t work_bytes, void* stream);
 
 /*
+ * zfpx_plan_encode_var for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same launches and results, with the staging area in a file-scope device
+ * array of zfpx_noalloc_scratch_bytes() bytes (32 MiB) instead of a caller
+ * workspace.  It calls no hipMalloc, hipFree or allocating routine.
+ *   Limit: the plan's staging area, (2*rate_cap*nblocks + ceil(nblocks/64))
+ *   32-bit words rounded up to whole 64-block tiles, must fit the array;
+ *   ENOSPC otherwise (nothing enqueued).  At rate_cap 16 that is about
+ *   262,000 blocks (16.7M values).
+ *   Each GPU holds its own copy of the array, set up on the first call on that
+ *   device (EHIP if the runtime cannot give its address) and kept until the
+ *   process ends.  Every call on one GPU uses the same array and the last
+ *   call's contents stay in it (nothing in it needs to start at zero): calls
+ *   that overlap in time on one GPU race and give wrong streams.
+ * Other arguments and errors as zfpx_plan_encode_var.
+ */
+int zfpx_plan_encode_var_noalloc(const zfpx_plan* plan, const float* d_src, int64_t src_elems,
+                                 int maxprec, int minexp, int rate_cap, uint32_t* d_words,
+                                 size_t words_bytes, uint8_t* d_nd, int64_t* d_tile_off,
+                                 void* stream);
+size_t zfpx_noalloc_scratch_bytes(void);
+
+/*
  * Decode a stream made by zfpx_plan_encode_var with the same plan and
  * parameters into the plan's points of d_dst.  Any content of the words,
  * counts and offsets decodes without a fault: counts are clamped to

@@ -533,6 +533,23 @@ int zfpx_plan_encode_var(const zfpx_plan* p, const float* d_src, int64_t src_ele
   return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
 }
 
+int zfpx_plan_encode_var_noalloc(const zfpx_plan* p, const float* d_src, int64_t src_elems,
+                                 int maxprec, int minexp, int rate_cap, uint32_t* d_words,
+                                 size_t words_bytes, uint8_t* d_nd, int64_t* d_tile_off,
+                                 void* stream) {
+  if (!p || !var_params_ok(maxprec, minexp, rate_cap)) return ZFPX_EINVAL;
+  if (p->nblocks == 0) return ZFPX_OK;
+  const size_t need =
+      (var_stage_words(p->nblocks, rate_cap) + (size_t)(p->nblocks + 63) / 64) * sizeof(uint32_t);
+  if (need > kNoAllocScratchBytes) return ZFPX_ENOSPC;
+  void* work = nullptr;
+  if (noalloc_scratch(&work) != hipSuccess) return ZFPX_EHIP;
+  return zfpx_plan_encode_var(p, d_src, src_elems, maxprec, minexp, rate_cap, d_words,
+                              words_bytes, d_nd, d_tile_off, work, kNoAllocScratchBytes, stream);
+}
+
+size_t zfpx_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
 int zfpx_plan_decode_var(const zfpx_plan* p, const uint32_t* d_words, size_t words_bytes,
                          const uint8_t* d_nd, const int64_t* d_tile_off, int maxprec, int minexp,
                          int rate_cap, float* d_dst, int64_t dst_elems, void* stream) {

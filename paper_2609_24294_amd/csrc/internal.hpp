@@ -74,6 +74,11 @@ hipError_t launch_plan_decode_var(const PlanDev& p, bool vec4, const uint32_t* i
                                   uint64_t in_words, const uint8_t* nd, const int64_t* tile_off,
                                   float* dst, int cap, int32_t nblocks, int maxprec, int minexp,
                                   hipStream_t s);
+// Scratch of the allocation-free variable-size encoder: a file-scope device
+// array of kNoAllocScratchBytes (kernels.hip), one copy per GPU.  Returns its
+// address on the current device (looked up once per device).
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_var_chunk_offsets(const int64_t* chunk_first, int32_t nchunks,
                                     const uint8_t* nd, const int64_t* tile_off,
                                     int64_t* chunk_off, hipStream_t s);

@@ -12,6 +12,8 @@
 // one-tile-per-wave launch and as a persistent launch.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "block_codec.hpp"
 #include "internal.hpp"
 
@@ -1377,6 +1379,38 @@ hipError_t launch_var_chunk_offsets(const int64_t* chunk_first, int32_t nchunks,
   hipLaunchKernelGGL(k_var_chunk_offsets, dim3((nchunks + 1 + 255) / 256), dim3(256), 0, s,
                      chunk_first, nchunks, nd, tile_off, chunk_off);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free variable-size encoder
+// ---------------------------------------------------------------------------
+// The staging slots and tile counts of one variable-size encode, for callers
+// that cannot allocate.  Every GPU the library runs on holds its own copy of
+// the array until the process ends.  In host code the array's name is not a
+// device address: host code uses only the address hipGetSymbolAddress gives
+// for the current device.
+static __device__ __align__(256) uint32_t scratch[kNoAllocScratchBytes / sizeof(uint32_t)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace zfpx

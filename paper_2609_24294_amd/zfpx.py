@@ -73,6 +73,9 @@ _SIGS = {
     "zfpx_plan_var_sizes": (_INT, [_P, _INT, _PI64, _PI64, _c.POINTER(_SZ)]),
     "zfpx_plan_encode_var": (_INT, [_P, _P, _I64, _INT, _INT, _INT, _P, _SZ, _P, _P, _P, _SZ,
                                     _P]),
+    "zfpx_plan_encode_var_noalloc": (_INT, [_P, _P, _I64, _INT, _INT, _INT, _P, _SZ, _P, _P,
+                                            _P]),
+    "zfpx_noalloc_scratch_bytes": (_SZ, []),
     "zfpx_plan_decode_var": (_INT, [_P, _P, _SZ, _P, _P, _INT, _INT, _INT, _P, _I64, _P]),
     "zfpx_plan_var_chunk_offsets": (_INT, [_P, _P, _P, _P, _P]),
     "f16_truncate": (_INT, [_P, _SZ, _P, _P]),
@@ -359,6 +362,22 @@ def zfpx_plan_encode_var(plan: Plan, src: torch.Tensor, maxprec: int, minexp: in
                                      _dev(work), _nbytes(work), _stream(stream)),
            "zfpx_plan_encode_var")
     return words, nd, tile_off
+
+
+def zfpx_plan_encode_var_noalloc(plan: Plan, src: torch.Tensor, maxprec: int, minexp: int,
+                                 rate_cap: int, words: torch.Tensor, nd: torch.Tensor,
+                                 tile_off: torch.Tensor, stream=None) -> None:
+    """zfpx_plan_encode_var with the library's own device scratch instead of
+    a workspace: no allocation on the call (outputs are the caller's)."""
+    _check(_lib.zfpx_plan_encode_var_noalloc(plan.handle, _dev(src, torch.float32), src.numel(),
+                                             maxprec, minexp, rate_cap, _dev(words),
+                                             _nbytes(words), _dev(nd, torch.uint8),
+                                             _dev(tile_off, torch.int64), _stream(stream)),
+           "zfpx_plan_encode_var_noalloc")
+
+
+def zfpx_noalloc_scratch_bytes() -> int:
+    return int(_lib.zfpx_noalloc_scratch_bytes())
 
 
 def zfpx_plan_decode_var(plan: Plan, words: torch.Tensor, nd: torch.Tensor,
