@@ -90,12 +90,15 @@ _SIGS = {
 
 
 def lib():
-    """Load liboracle.so (building it first if it is missing)."""
+    """Load liboracle.so (building it first if it is missing).  The
+    environment variable ZFPX_ORACLE_LIB names another build of the same
+    source to load instead (the tests' sanitizer run uses it)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("ZFPX_ORACLE_LIB") or LIB_PATH
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(path)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
             f.restype = res
@@ -240,6 +243,8 @@ def decode_regular(words, shape, rate, fill=0.0):
     nz, ny, nx = shape
     a = np.full(nz * ny * nx, fill, np.float32)
     w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size < regular_blocks(nx, ny, nz) * int(rate):
+        raise ValueError("stream shorter than rate words per block")
     lib().orc_decode_regular(w, nx, ny, nz, 1, nx, nx * ny, int(rate), a)
     return a.reshape(shape)
 
@@ -268,6 +273,8 @@ def decode_unpack(chunks, words, rate, dst):
     """Decode into `dst` (float32, modified in place; only chunk points written)."""
     assert dst.dtype == np.float32 and dst.flags.c_contiguous
     w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size < int(chunk_blocks(chunks).sum()) * int(rate):
+        raise ValueError("stream shorter than rate words per block")
     lib().orc_decode_unpack(*_chunk_args(chunks), w, int(rate), dst.reshape(-1))
     return dst
 
@@ -285,6 +292,9 @@ def decode_sample(chunks, words, rate, ids):
     """Decode the listed blocks: returns (values (n,64), offsets (n,64), inside (n,64))."""
     w = np.ascontiguousarray(words, dtype=np.uint64)
     ids = np.ascontiguousarray(ids, dtype=np.int64)
+    if ids.size and (ids.min() < 0 or ids.max() >= int(chunk_blocks(chunks).sum())
+                     or w.size < (int(ids.max()) + 1) * int(rate)):
+        raise ValueError("block id outside the plan or stream too short")
     vals = np.zeros((ids.size, 64), np.float32)
     pos = np.zeros((ids.size, 64), np.int64)
     ins = np.zeros((ids.size, 64), np.int32)

@@ -13,7 +13,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libzfpx.so")
-SOURCES = ["kernels.hip", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "server.cpp", "plan_tables.cpp"]
 
 # packed FP32 instructions are disabled on purpose; plain float code only
 HIPCC_FLAGS = [

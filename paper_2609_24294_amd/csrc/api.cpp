@@ -20,7 +20,7 @@ using namespace zfpx;
 
 namespace {
 
-constexpr int64_t kMaxBlocks = 0x7fffffffLL;
+constexpr int64_t kMaxBlocks = kMaxPlanBlocks;
 
 bool rate_ok(int rate) { return rate >= 1 && rate <= 32; }
 int64_t ceil4(int64_t n) { return (n + 3) / 4; }
@@ -162,121 +162,47 @@ int zfpx_plan_destroy(zfpx_plan* p) {
 int zfpx_plan_create(int32_t nchunks, const int64_t* chunk_base, const int64_t* level_stride,
                      const int32_t* levels, const int32_t* row_start, const int64_t* row_offset,
                      const int32_t* row_len, zfpx_plan** out) {
-  if (!out || nchunks < 0) return ZFPX_EINVAL;
+  if (!out) return ZFPX_EINVAL;
   *out = nullptr;
-  if (nchunks > 0 && (!chunk_base || !level_stride || !levels || !row_start)) return ZFPX_EINVAL;
-  if (nchunks > 0 && row_start[0] != 0) return ZFPX_EINVAL;
-  for (int c = 0; c < nchunks; c++) {
-    if (row_start[c + 1] < row_start[c] || levels[c] < 0 || level_stride[c] < 0 ||
-        chunk_base[c] < 0)
-      return ZFPX_EINVAL;
-  }
-  int64_t nrows_total = nchunks > 0 ? row_start[nchunks] : 0;
-  if (nrows_total > 0 && (!row_offset || !row_len)) return ZFPX_EINVAL;
-  for (int64_t r = 0; r < nrows_total; r++)
-    if (row_len[r] < 1 || row_offset[r] < 0) return ZFPX_EINVAL;
-
+  PlanTables t;
+  if (build_plan_tables(nchunks, chunk_base, level_stride, levels, row_start, row_offset, row_len,
+                        &t) != 0)
+    return ZFPX_EINVAL;
   zfpx_plan* p = new (std::nothrow) zfpx_plan();
   if (!p) return ZFPX_ENOMEM;
   p->nchunks = nchunks;
-  p->chunk_blocks.assign(nchunks, 0);
-  p->chunk_first.assign(nchunks + 1, 0);
-  std::vector<SegDesc> segs;
-  std::vector<int32_t> seg_block0;
-  int64_t total = 0, values = 0, min_elems = 0;
-  bool vec4 = true;
-  for (int c = 0; c < nchunks; c++) {
-    int64_t r0 = row_start[c], nrows = row_start[c + 1] - r0, L = levels[c];
-    int64_t ngroups = ceil4(nrows);
-    std::vector<int64_t> width(ngroups, 0);
-    for (int64_t g = 0; g < ngroups; g++)
-      for (int64_t r = 4 * g; r < std::min(4 * g + 4, nrows); r++)
-        width[g] = std::max<int64_t>(width[g], row_len[r0 + r]);
-    int64_t per_lb = 0;
-    for (int64_t g = 0; g < ngroups; g++) per_lb += ceil4(width[g]);
-    int64_t cb = (L > 0 && nrows > 0) ? ceil4(L) * per_lb : 0;
-    p->chunk_first[c] = total;
-    p->chunk_blocks[c] = cb;
-    if (cb > 0) {
-      if ((level_stride[c] & 3) != 0 || (chunk_base[c] & 3) != 0) vec4 = false;
-      for (int64_t r = r0; r < r0 + nrows; r++) {
-        if ((row_offset[r] & 3) != 0) vec4 = false;
-        values += L * row_len[r];
-        min_elems = std::max(min_elems, chunk_base[c] + (L - 1) * level_stride[c] + row_offset[r] +
-                                            row_len[r]);
-      }
-      for (int64_t bz = 0; bz < ceil4(L); bz++) {
-        for (int64_t g = 0; g < ngroups; g++) {
-          SegDesc d{};
-          for (int dy = 0; dy < 4; dy++) {
-            int64_t r = r0 + std::min<int64_t>(4 * g + dy, nrows - 1);
-            d.rbase[dy] = chunk_base[c] + 4 * bz * level_stride[c] + row_offset[r];
-            d.rlen[dy] = row_len[r];
-          }
-          d.lstride = level_stride[c];
-          d.block0 = (int32_t)(total + bz * per_lb);  // fixed below if it overflows
-          d.nbx = (int32_t)ceil4(width[g]);
-          d.nlev = (int32_t)std::min<int64_t>(4, L - 4 * bz);
-          d.nrow = (int32_t)std::min<int64_t>(4, nrows - 4 * g);
-          segs.push_back(d);
-        }
-      }
-      // block0 of each run: running sum in run order
-      int64_t run = total;
-      for (size_t i = segs.size() - (size_t)(ceil4(L) * ngroups); i < segs.size(); i++) {
-        segs[i].block0 = (int32_t)std::min<int64_t>(run, kMaxBlocks);
-        run += segs[i].nbx;
-      }
-    }
-    total += cb;
-    if (total > kMaxBlocks) {
-      delete p;
-      return ZFPX_EINVAL;
-    }
-  }
-  p->chunk_first[nchunks] = total;
-  p->nblocks = total;
-  p->nvalues = values;
-  p->min_elems = min_elems;
-  p->vec4 = vec4;
-  p->shape_key = {nchunks, total, values, (int64_t)segs.size()};
-
-  // run starts and the tile -> run table
-  seg_block0.resize(segs.size() + 1);
-  for (size_t i = 0; i < segs.size(); i++) seg_block0[i] = segs[i].block0;
-  seg_block0[segs.size()] = (int32_t)total;
-  int64_t ntiles = (total + 63) / 64;
-  std::vector<int32_t> tile_seg(std::max<int64_t>(ntiles, 1), 0);
-  size_t s = 0;
-  for (int64_t t = 0; t < ntiles; t++) {
-    int64_t b = 64 * t;
-    while (s + 1 < segs.size() && seg_block0[s + 1] <= b) s++;
-    tile_seg[t] = (int32_t)s;
-  }
+  p->chunk_blocks = t.chunk_blocks;
+  p->chunk_first = t.chunk_first;
+  p->nblocks = t.nblocks;
+  p->nvalues = t.nvalues;
+  p->min_elems = t.min_elems;
+  p->vec4 = t.vec4;
+  p->shape_key = {nchunks, t.nblocks, t.nvalues, (int64_t)t.segs.size()};
+  const std::vector<SegDesc>& segs = t.segs;
   if (!segs.empty()) {
-    size_t nseg = segs.size();
+    const size_t nseg = segs.size();
     if (hipMalloc(&p->d_segs, nseg * sizeof(SegDesc)) != hipSuccess ||
         hipMalloc(&p->d_seg_block0, (nseg + 1) * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&p->d_tile_seg, tile_seg.size() * sizeof(int32_t)) != hipSuccess) {
+        hipMalloc(&p->d_tile_seg, t.tile_seg.size() * sizeof(int32_t)) != hipSuccess) {
       zfpx_plan_destroy(p);
       return ZFPX_ENOMEM;
     }
     if (hipMemcpy(p->d_segs, segs.data(), nseg * sizeof(SegDesc), hipMemcpyHostToDevice) !=
             hipSuccess ||
-        hipMemcpy(p->d_seg_block0, seg_block0.data(), (nseg + 1) * sizeof(int32_t),
+        hipMemcpy(p->d_seg_block0, t.seg_block0.data(), (nseg + 1) * sizeof(int32_t),
                   hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_tile_seg, tile_seg.data(), tile_seg.size() * sizeof(int32_t),
+        hipMemcpy(p->d_tile_seg, t.tile_seg.data(), t.tile_seg.size() * sizeof(int32_t),
                   hipMemcpyHostToDevice) != hipSuccess) {
       zfpx_plan_destroy(p);
       return ZFPX_EHIP;
     }
   }
-  if (total > 0) {
-    if (hipMalloc(&p->d_chunk_first, (nchunks + 1) * sizeof(int64_t)) != hipSuccess) {
+  if (t.nblocks > 0) {
+    if (hipMalloc(&p->d_chunk_first, ((size_t)nchunks + 1) * sizeof(int64_t)) != hipSuccess) {
       zfpx_plan_destroy(p);
       return ZFPX_ENOMEM;
     }
-    if (hipMemcpy(p->d_chunk_first, p->chunk_first.data(), (nchunks + 1) * sizeof(int64_t),
+    if (hipMemcpy(p->d_chunk_first, p->chunk_first.data(), ((size_t)nchunks + 1) * sizeof(int64_t),
                   hipMemcpyHostToDevice) != hipSuccess) {
       zfpx_plan_destroy(p);
       return ZFPX_EHIP;

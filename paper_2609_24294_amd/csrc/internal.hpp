@@ -6,19 +6,9 @@
 
 #include <vector>
 
-namespace zfpx {
+#include "plan_tables.hpp"
 
-// One run of x-blocks: (chunk, level block, row group).  Each lane finds the
-// run holding its block and gathers/scatters its 4x4x4 values through it.
-struct SegDesc {
-  int64_t rbase[4];  // element offset of row (4g+dy, clamped) at level 4*bz
-  int64_t lstride;   // elements between levels
-  int32_t block0;    // first global block id of the run
-  int32_t nbx;       // x blocks in the run
-  int32_t nlev;      // levels present in this level block (1..4)
-  int32_t nrow;      // rows present in this row group (1..4)
-  int32_t rlen[4];   // row lengths (missing rows repeat the last row)
-};
+namespace zfpx {
 
 // Device-side view of a plan.
 struct PlanDev {
