@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter calibration)")
     ap.add_argument("--serving-requests", type=int, default=10000)
+    ap.add_argument("--serving-workgroups", type=int, default=0,
+                    help="workgroups of the serving loop (0: the library's default)")
     return ap.parse_args()
 
 
@@ -287,7 +289,8 @@ def main():
     if "serving" in legs:
         torch.cuda.empty_cache()
         try:
-            serving = serving_report(torch, zfpx, W, args.serving_requests)
+            serving = serving_report(torch, zfpx, W, args.serving_requests,
+                                     args.serving_workgroups)
         except zfpx.ZfpxError as e:
             serving = {"error": str(e)}
     if "cpu" in legs:
@@ -811,7 +814,7 @@ def batching_report(torch, zfpx, W, rate=16, reps=10):
             "tuned": tuned}
 
 
-def serving_report(torch, zfpx, W, count):
+def serving_report(torch, zfpx, W, count, workgroups=0):
     """Poisson arrivals of mixed compress/decompress requests (64 KB .. 64 MB of
     float32, rate 8/16/32): the saturated throughput of the serving loop and
     of one launch per request (every request at t = 0), then p50/p99 latency
@@ -866,7 +869,7 @@ def serving_report(torch, zfpx, W, count):
     log(f"serving: saturated throughput ({count} requests at t = 0), both forms")
     lat = zfpx.zfpx_plain_replay(reqs, zero, timeout_s=60.0)
     sat = nbytes.sum() / lat.max()
-    sv = zfpx.Server(64 << 30, max_slots=1024)
+    sv = zfpx.Server(64 << 30, max_slots=1024, workgroups=workgroups)
     try:
         lat_s = sv.replay(reqs, zero, timeout_s=60.0)
     finally:
@@ -874,6 +877,7 @@ def serving_report(torch, zfpx, W, count):
     sat_s = nbytes.sum() / lat_s.max()
     mean_bytes = nbytes.mean()
     out = {"requests_per_point": count, "budget_bytes": 64 << 30,
+           "loop_workgroups": workgroups or "library default",
            "saturated_gbs_fp32": {"server": round(sat_s / 1e9, 1),
                                   "per_request_launch": round(sat / 1e9, 1)},
            "mean_request_mb": round(mean_bytes / 1e6, 2),
@@ -890,7 +894,7 @@ def serving_report(torch, zfpx, W, count):
             arena = torch.empty(sum(out_words(q) for q in stream), dtype=torch.int64, device=dev)
         reqs, nbytes, outs = build(stream, arena)
         log(f"serving: load {load:.2f}, mean gap {gap * 1e6:.1f} us")
-        sv = zfpx.Server(64 << 30, max_slots=1024)
+        sv = zfpx.Server(64 << 30, max_slots=1024, workgroups=workgroups)
         try:
             ls = sv.replay(reqs, arrival, timeout_s=60.0)
         finally:

@@ -494,7 +494,14 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
         const int p = parse_groups(window64(in, pos), ev);
         const int m = popc64(ev);
         const int last = n + p + 1 - m;  // coefficient of the last one found
-        if (p < 63 && pos + (uint32_t)p < maxbits && last <= 62) {
+        // The whole run can be read off the window unless it reaches past
+        // it, past the budget, or up to the implied coefficient 63; then it
+        // is taken group by group (the second stage runs no step when the
+        // first applied: one stage after the other, not alternatives, keeps
+        // the compiler from carrying this block's planes through a loop
+        // around the decoder in extra registers).
+        const bool whole = p < 63 && pos + (uint32_t)p < maxbits && last <= 62;
+        if (whole) {
           // each coefficient-one moves down by the number of group tests
           // before it: y = ev - sum_t (ev without its lowest t ones) >> t
           uint64_t y = ev, e = ev;
@@ -506,25 +513,24 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
           x |= y << n;
           n = last + 1;
           pos += (uint32_t)p + 2;  // through the closing group test 0
-        } else {
-          // group by group from the first scan: zeros up to the next one,
-          // at most up to coefficient 63 (implied) or the end of the budget
-          int g = 1;
-          while (g) {
-            int lim = 63 - n;
-            if ((int)(maxbits - pos) < lim) lim = (int)(maxbits - pos);
-            const uint64_t s = window64(in, pos);
-            const int z = s ? ctz64(s) : 64;
-            const int t = z < lim ? z : lim;
-            const int found = z < lim;
-            x |= uint64_t(1) << (n + t);
-            n += t + 1;
-            pos += (uint32_t)(t + found);
-            g = 0;
-            if (n < 64 && pos < maxbits) {
-              g = (int)((s >> (t + found)) & 1);  // t + found <= 63
-              pos += 1;
-            }
+        }
+        // group by group: zeros up to the next one, at most up to
+        // coefficient 63 (implied) or the end of the budget
+        int g = whole ? 0 : 1;
+        while (g) {
+          int lim = 63 - n;
+          if ((int)(maxbits - pos) < lim) lim = (int)(maxbits - pos);
+          const uint64_t s = window64(in, pos);
+          const int z = s ? ctz64(s) : 64;
+          const int t = z < lim ? z : lim;
+          const int found = z < lim;
+          x |= uint64_t(1) << (n + t);
+          n += t + 1;
+          pos += (uint32_t)(t + found);
+          g = 0;
+          if (n < 64 && pos < maxbits) {
+            g = (int)((s >> (t + found)) & 1);  // t + found <= 63
+            pos += 1;
           }
         }
         vm = mask_upto(n);  // n >= 1 after a group test of 1

@@ -12,6 +12,7 @@
 // one-tile-per-wave launch and as a persistent launch.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <mutex>
 
 #include "block_codec.hpp"
@@ -847,7 +848,13 @@ __device__ __forceinline__ uint32_t sys_load32(const uint32_t* p) {
 __device__ __forceinline__ uint64_t dev_load(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
+// Every memory access before this point has completed before any access
+// after it is issued; the compiler fences keep the accesses on their sides.
+__device__ __forceinline__ void wait_memory() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 __device__ __forceinline__ int32_t dev_load32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -894,6 +901,7 @@ __device__ __forceinline__ void serve_tile(const ServeDesc& q, int lane, uint64_
 }
 
 constexpr int kDescWords = sizeof(ServeDesc) / sizeof(uint64_t);
+static_assert(offsetof(ServeDesc, seq) == 0, "seq is descriptor word 0");
 static_assert(sizeof(ServeDesc) % sizeof(uint64_t) == 0, "descriptor is whole words");
 static_assert(kDescWords <= 64, "one descriptor word per lane");
 
@@ -912,17 +920,34 @@ __device__ __forceinline__ void serve_dispatch(const ServeDev d, int lane, uint6
     }
     const uint64_t hpub = sys_load(&d.ctl->published);
     if (hpub > seen) {
-      for (uint64_t sq = seen; sq < hpub; sq++) {  // one descriptor word per lane
+      // A slot is rewritten once its previous request has completed, but a
+      // worker that claimed past the end of that request may still be reading
+      // it.  So seq (word 0) is first marked invalid, then the other words are
+      // copied, then seq, each step complete before the next: a reader that
+      // finds the same seq before and after reading the other words has read
+      // one whole descriptor.  (The requests seen .. hpub-1 lie in distinct
+      // slots: a slot is reused only after its request completed.)
+      for (uint64_t sq = seen; sq < hpub; sq++) {
         const int slot = (int)(sq % (uint64_t)d.cap);
-        const uint64_t* from = reinterpret_cast<const uint64_t*>(d.ring + slot);
-        uint64_t* to = reinterpret_cast<uint64_t*>(d.ring_dev + slot);
-        if (lane < kDescWords)
-          __hip_atomic_store(to + lane,
-                             __hip_atomic_load(from + lane, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_SYSTEM),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (lane == 0)
+          __hip_atomic_store(&d.ring_dev[slot].seq, ~uint64_t(0), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_SYSTEM);
       }
-      wait_memory();  // the copies are in memory before they are published
+      wait_memory();
+      for (int pass = 0; pass < 2; pass++) {
+        // pass 0: every word but seq (one word per lane); pass 1: seq
+        for (uint64_t sq = seen; sq < hpub; sq++) {
+          const int slot = (int)(sq % (uint64_t)d.cap);
+          const uint64_t* from = reinterpret_cast<const uint64_t*>(d.ring + slot);
+          uint64_t* to = reinterpret_cast<uint64_t*>(d.ring_dev + slot);
+          if (pass == 0 ? lane >= 1 && lane < kDescWords : lane == 0)
+            __hip_atomic_store(to + lane,
+                               __hip_atomic_load(from + lane, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_SYSTEM),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        wait_memory();  // complete before seq is written / before publishing
+      }
       if (lane == 0)
         __hip_atomic_store(&d.dctl->published, hpub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       seen = hpub;
@@ -1024,8 +1049,12 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
     if (!have_q || qtag != gtag) {
       const ServeDesc* r = d.ring_dev + slot;
       // coherent vector loads, kept in scalar registers (every lane read the
-      // same words)
-      q.seq = uniform64(dev_load(&r->seq));
+      // same words).  seq is read before and after the other words: if the
+      // claimed request has completed, the dispatcher may be rewriting the
+      // slot for a later one, and only a descriptor whose seq did not change
+      // across the reads is whole.
+      const uint64_t seq0 = uniform64(dev_load(&r->seq));
+      wait_memory();
       q.ntiles = __builtin_amdgcn_readfirstlane(dev_load32(&r->ntiles));
       q.op = __builtin_amdgcn_readfirstlane(dev_load32(&r->op));
       q.rate = __builtin_amdgcn_readfirstlane(dev_load32(&r->rate));
@@ -1043,11 +1072,14 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
       q.geo.nby = __builtin_amdgcn_readfirstlane(dev_load32(&r->geo.nby));
       q.in = uniform64(dev_load(&r->in));
       q.out = uniform64(dev_load(&r->out));
+      wait_memory();
+      q.seq = uniform64(dev_load(&r->seq));
       qtag = gtag;
-      have_q = (uint32_t)q.seq == gtag;
+      have_q = q.seq == seq0 && (uint32_t)q.seq == gtag;
       if (!have_q) {
-        // the request finished and the slot already holds the next one's
-        // descriptor (its claim counter not reset yet): nothing to do here
+        // the claimed request finished and the slot holds (or is being
+        // rewritten for) a later one whose claim counter is not moved on
+        // yet: nothing to do here
         cursor++;
         continue;
       }
