@@ -347,8 +347,17 @@ ZFPX_HD uint32_t encode_block(float* v, uint64_t* out, int rate_rt, int maxprec 
   uint64_t X[32];
   {
     int32_t q[64];
+    if (emax >= -97) {
+      // 2^(30 - emax) is a normal float: one multiply per value is the same
+      // exact scaling (a product below 1 in magnitude truncates to 0 whatever
+      // its rounding)
+      const float sc = scale_pow2(1.0f, 30 - emax);
 #pragma unroll
-    for (int i = 0; i < 64; i++) q[i] = (int32_t)scale_pow2(v[i], 30 - emax);
+      for (int i = 0; i < 64; i++) q[i] = (int32_t)(v[i] * sc);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 64; i++) q[i] = (int32_t)scale_pow2(v[i], 30 - emax);
+    }
     xform_fwd(q);
     // negabinary (q + mask) ^ mask: the add here, the XOR in the transpose
 #pragma unroll
@@ -373,25 +382,32 @@ ZFPX_HD uint32_t encode_block(float* v, uint64_t* out, int rate_rt, int maxprec 
         uint64_t y = x >> n;  // bits not yet significant (n < 64 here)
         // Each newly significant coefficient costs a group test 1, the zeros
         // up to it and its own 1 (that one is implied, and not written, for
-        // coefficient 63).  Common case: all of the plane's groups fit one
-        // 64-bit code word and none reaches coefficient 63; the word is then
-        // written at once.  Groups that start past the budget only land in
-        // the slack words, and the budget is spent either way, so the coded
-        // bits are those of the group-by-group loop below.
+        // coefficient 63).
         bool done = false;
-        uint64_t code = 0, r = y;
-        int len = 0, c = 0;
-        while (r != 0) {
-          int p = ctz64(r);
-          code |= (uint64_t(1) | (uint64_t(2) << p)) << (len & 63);
-          len += p + 2;
-          c += p + 1;
-          r = (r >> p) >> 1;
-        }
-        if (len <= 64 && n + c <= 63) {
+        // Common case: all of the plane's groups fit one 64-bit code word and
+        // none reaches coefficient 63.  With the newly significant
+        // coefficients at positions q_0 < ... < q_(m-1) of y, the word has a
+        // group test 1 at bit 0 and, for each i, the coefficient's one at bit
+        // q_i + i + 1, followed (unless i is the last) by the next group test
+        // 1 at bit q_i + i + 2.  sp = sum_i 2^(q_i + i) (each one of y moved
+        // up by the number of ones below it) is built by adding, for t = 0,
+        // 1, ..., y without its lowest t + 1 ones shifted up by t.  The word
+        // is then written at once; groups that start past the budget only
+        // land in the slack words, and the budget is spent either way, so the
+        // coded bits are those of the group-by-group loop below.
+        const int hy = 63 - __builtin_clzll(y);           // q_(m-1)
+        const int hs = hy + __builtin_popcountll(y) - 1;  // its bit in sp
+        if (hs <= 62 && n + hy <= 62) {
+          uint64_t sp = y, e = y;
+          for (int t = 0;; t++) {
+            e &= e - 1;
+            if (e == 0) break;
+            sp += e << t;
+          }
+          const uint64_t code = 1 | (sp << 1) | ((sp ^ (uint64_t(1) << hs)) << 2);
           or_bits(out, pos, code);
-          pos += len;
-          n += c;
+          pos += (uint32_t)hs + 2;
+          n += hy + 1;
           done = true;
         }
         while (!done && y != 0 && pos < maxbits) {
@@ -548,9 +564,11 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
   }
   xform_inv(q);
   if (emax >= -95) {
-    // float(q) is one rounding and the power-of-two scale is exact (normal result)
+    // float(q) is one rounding and the power-of-two scale is exact (normal
+    // result); 2^(emax - 30) is a normal float, so a multiply applies it
+    const float sc = scale_pow2(1.0f, emax - 30);
 #pragma unroll
-    for (int i = 0; i < 64; i++) vout[i] = scale_pow2((float)q[i], emax - 30);
+    for (int i = 0; i < 64; i++) vout[i] = (float)q[i] * sc;
   } else {
     // results may be subnormal: round once from the exact double product
 #pragma unroll

@@ -1097,30 +1097,23 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
 }
 
 // float16 comparator; unaligned buffers take one value per thread.
-// Truncate: groups of 8 values (two 16-byte loads, one 16-byte store); each
-// thread takes four groups a whole grid apart, so eight loads are in flight.
+// Truncate: groups of 8 values (two 16-byte loads, one 16-byte store), one
+// group per thread on a grid that covers the buffer (the loop only runs more
+// than once beyond kElementwiseMaxBlocks workgroups): many short-lived
+// wavefronts keep more loads in flight than a capped grid whose threads walk
+// several groups.
 __global__ __launch_bounds__(256) void k_f16_truncate_v8(const float4* __restrict__ in,
                                                          size_t n8, uint4* __restrict__ out) {
   const size_t T = (size_t)gridDim.x * blockDim.x;
   auto h = [](float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f); };
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8; i += 4 * T) {
-    float4 a[4], b[4];
-#pragma unroll
-    for (int k = 0; k < 4; k++)
-      if (i + k * T < n8) {
-        a[k] = in[2 * (i + k * T)];
-        b[k] = in[2 * (i + k * T) + 1];
-      }
-#pragma unroll
-    for (int k = 0; k < 4; k++)
-      if (i + k * T < n8) {
-        uint4 r;
-        r.x = h(a[k].x) | (h(a[k].y) << 16);
-        r.y = h(a[k].z) | (h(a[k].w) << 16);
-        r.z = h(b[k].x) | (h(b[k].y) << 16);
-        r.w = h(b[k].z) | (h(b[k].w) << 16);
-        out[i + k * T] = r;
-      }
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8; i += T) {
+    const float4 a = in[2 * i], b = in[2 * i + 1];
+    uint4 r;
+    r.x = h(a.x) | (h(a.y) << 16);
+    r.y = h(a.z) | (h(a.w) << 16);
+    r.z = h(b.x) | (h(b.y) << 16);
+    r.w = h(b.z) | (h(b.w) << 16);
+    out[i] = r;
   }
 }
 
@@ -1294,6 +1287,15 @@ static unsigned elementwise_grid(size_t work) {
   return (unsigned)(g > 0 ? g : 1);
 }
 
+// One thread per work item, up to kElementwiseMaxBlocks workgroups of 256
+// (2^31 threads; the kernels loop beyond that).
+constexpr size_t kElementwiseMaxBlocks = size_t(1) << 23;
+static unsigned covering_grid(size_t work) {
+  size_t g = (work + 255) / 256;
+  if (g > kElementwiseMaxBlocks) g = kElementwiseMaxBlocks;
+  return (unsigned)(g > 0 ? g : 1);
+}
+
 hipError_t launch_serve(const ServeDev& d, int workgroups, hipStream_t s) {
   size_t shm = (size_t)kServeWaves * 64 * lds_stride(32) * sizeof(uint64_t);
   hipLaunchKernelGGL(k_serve, dim3(workgroups > 0 ? workgroups : 1), dim3(64 * kServeWaves), shm,
@@ -1306,7 +1308,7 @@ hipError_t launch_f16_truncate(const float* in, size_t n, uint16_t* out, hipStre
   size_t done = 0;
   if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0 && n >= 8) {
     size_t n8 = n / 8;
-    hipLaunchKernelGGL(k_f16_truncate_v8, dim3(elementwise_grid((n8 + 3) / 4)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_f16_truncate_v8, dim3(covering_grid(n8)), dim3(256), 0, s,
                        reinterpret_cast<const float4*>(in), n8, reinterpret_cast<uint4*>(out));
     done = n8 * 8;
   }
