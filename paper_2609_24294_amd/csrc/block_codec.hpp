@@ -553,14 +553,17 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
       }
       if (pos > maxbits) pos = maxbits;
     }
-    X[k] = x;
+    // odd planes complemented: after the transpose every coefficient is
+    // then XORed with the negabinary mask 0xaaaaaaaa (bits 1, 3, ..., 31)
+    X[k] = (k & 1) ? ~x : x;
   }
   transpose32x2(X);
   int32_t q[64];
 #pragma unroll
   for (int s = 0; s < 32; s++) {
-    q[kSeq.idx[s]] = (int32_t)(((uint32_t)X[s] ^ kNegabinaryMask) - kNegabinaryMask);
-    q[kSeq.idx[32 + s]] = (int32_t)(((uint32_t)(X[s] >> 32) ^ kNegabinaryMask) - kNegabinaryMask);
+    // negabinary to two's complement: (u ^ mask) - mask, the XOR done above
+    q[kSeq.idx[s]] = (int32_t)((uint32_t)X[s] - kNegabinaryMask);
+    q[kSeq.idx[32 + s]] = (int32_t)((uint32_t)(X[s] >> 32) - kNegabinaryMask);
   }
   xform_inv(q);
   if (emax >= -95) {

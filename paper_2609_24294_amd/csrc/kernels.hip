@@ -1124,21 +1124,15 @@ __global__ __launch_bounds__(256) void k_f16_truncate_s(const float* __restrict_
     out[i] = __builtin_bit_cast(uint16_t, (_Float16)in[i]);
 }
 
-// Restore: groups of 4 values (one 8-byte load, one 16-byte store); each
-// thread takes four groups a whole grid apart, so four loads are in flight.
+// Restore: groups of 4 values (one 8-byte load, one 16-byte store), one
+// group per thread on a covering grid, as truncate.
 __global__ __launch_bounds__(256) void k_f16_restore_v4(const uint2* __restrict__ in, size_t n4,
                                                         float4* __restrict__ out) {
   const size_t T = (size_t)gridDim.x * blockDim.x;
   auto f = [](uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)w); };
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += 4 * T) {
-    uint2 r[4];
-#pragma unroll
-    for (int k = 0; k < 4; k++)
-      if (i + k * T < n4) r[k] = in[i + k * T];
-#pragma unroll
-    for (int k = 0; k < 4; k++)
-      if (i + k * T < n4)
-        out[i + k * T] = make_float4(f(r[k].x), f(r[k].x >> 16), f(r[k].y), f(r[k].y >> 16));
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += T) {
+    const uint2 r = in[i];
+    out[i] = make_float4(f(r.x), f(r.x >> 16), f(r.y), f(r.y >> 16));
   }
 }
 
@@ -1323,7 +1317,7 @@ hipError_t launch_f16_restore(const uint16_t* in, size_t n, float* out, hipStrea
   size_t done = 0;
   if (((uintptr_t)in & 7) == 0 && ((uintptr_t)out & 15) == 0 && n >= 4) {
     size_t n4 = n / 4;
-    hipLaunchKernelGGL(k_f16_restore_v4, dim3(elementwise_grid((n4 + 3) / 4)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_f16_restore_v4, dim3(covering_grid(n4)), dim3(256), 0, s,
                        reinterpret_cast<const uint2*>(in), n4, reinterpret_cast<float4*>(out));
     done = n4 * 4;
   }
