@@ -597,12 +597,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // ---------------------------------------------------------------------------
 // Block b takes nd[b] = ceil(bits / 32) 32-bit words at word offset
 // nd[0] + ... + nd[b-1].  A tile's offset depends on every earlier tile's
-// size, so encoding runs in three launches that never wait on each other's
-// progress: (1) each wavefront codes its 64-block tile as in fixed rate and
-// writes the tile's words, compacted, to its own staging slot of 64 * 2 * cap
-// words, plus the per-block counts and the tile's count; (2) one workgroup
-// scans the tile counts into tile offsets; (3) each wavefront copies its
-// tile's words from the staging slot to the tile's offset.  The words, which
+// size, so encoding runs in stages that never wait on each other's progress:
+// (1) each wavefront codes its 64-block tile as in fixed rate and writes the
+// tile's words, compacted, to its own staging slot of 64 * 2 * cap words,
+// plus the per-block counts and the tile's count; (2) a chunked scan (three
+// short launches) turns the tile counts into tile offsets; (3) each wavefront
+// copies its tile's words from the staging slot to the tile's offset.  The words, which
 // are the bulk of the traffic, are stored as contiguous 256-byte stretches
 // per wavefront instruction in both (1) and (3).
 
@@ -673,47 +673,108 @@ __global__ __launch_bounds__(256) void k_encode_var(Geo geo, const float* __rest
 // workgroup walks the counts in chunks of 8192: a coalesced load into LDS,
 // each thread sums 8 consecutive counts, a workgroup scan of the thread sums
 // (wavefront scans, then the 16 wavefront totals), and 8 offsets per thread.
-__global__ __launch_bounds__(1024) void k_var_scan(const uint32_t* __restrict__ tile_count,
-                                                   int32_t ntiles, int64_t* __restrict__ tile_off) {
-  constexpr int kPer = 8, kChunk = 1024 * kPer;
-  __shared__ uint32_t buf[kChunk];
+// Tile offsets = exclusive prefix sum of the tile counts, in three launches
+// over chunks of kScanChunk counts (8 per thread of a 1024-thread group):
+// (1) each chunk's sum, parked in tile_off at the chunk's first position;
+// (2) one group scans the chunk sums in place into chunk bases and writes the
+// total at tile_off[ntiles]; (3) each chunk reads its base, then scans its
+// counts into tile_off.  Each launch reads and writes only positions the
+// previous one left ready, so no launch waits on another's progress.
+constexpr int kScanPer = 8, kScanChunk = 1024 * kScanPer;
+
+// Load chunk c's counts (zero past ntiles) and return this thread's eight
+// consecutive counts and their sum, with the group's exclusive prefix of sums
+// before this thread in *before and the chunk total in *total.
+__device__ __forceinline__ void scan_chunk_counts(const uint32_t* __restrict__ tile_count,
+                                                  int32_t ntiles, int64_t base, uint32_t* buf,
+                                                  uint32_t* wtot, uint32_t v[kScanPer],
+                                                  uint32_t* before, uint32_t* total) {
+  const int i = threadIdx.x, lane = i & 63, w = i >> 6;
+#pragma unroll
+  for (int j = 0; j < kScanPer; j++) {
+    const int64_t k = base + j * 1024 + i;
+    buf[j * 1024 + i] = k < ntiles ? tile_count[k] : 0u;
+  }
+  __syncthreads();
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; j++) {
+    v[j] = buf[i * kScanPer + j];
+    sum += v[j];
+  }
+  const uint32_t incl = wave_incl_scan(sum, lane);
+  if (lane == 63) wtot[w] = incl;
+  __syncthreads();
+  uint32_t b = 0, t = 0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const uint32_t x = wtot[k];
+    b += k < w ? x : 0u;
+    t += x;
+  }
+  *before = b + (incl - sum);
+  *total = t;
+}
+
+__global__ __launch_bounds__(1024) void k_var_scan_sums(const uint32_t* __restrict__ tile_count,
+                                                        int32_t ntiles,
+                                                        int64_t* __restrict__ tile_off) {
+  __shared__ uint32_t buf[kScanChunk];
   __shared__ uint32_t wtot[16];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint32_t v[kScanPer], before, total;
+  scan_chunk_counts(tile_count, ntiles, base, buf, wtot, v, &before, &total);
+  if (threadIdx.x == 0) tile_off[base] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_var_scan_bases(int32_t nchunks, int32_t ntiles,
+                                                         int64_t* __restrict__ tile_off) {
+  __shared__ int64_t wtot[16];
   const int i = threadIdx.x, lane = i & 63, w = i >> 6;
   int64_t carry = 0;
-  for (int32_t base = 0; base < ntiles; base += kChunk) {
+  for (int32_t c0 = 0; c0 < nchunks; c0 += 1024) {
+    const int32_t c = c0 + i;
+    const int64_t x = c < nchunks ? tile_off[(int64_t)c * kScanChunk] : 0;
+    int64_t incl = x;
 #pragma unroll
-    for (int j = 0; j < kPer; j++) {
-      const int32_t k = base + j * 1024 + i;
-      buf[j * 1024 + i] = k < ntiles ? tile_count[k] : 0u;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
     }
-    __syncthreads();
-    uint32_t v[kPer], sum = 0;
-#pragma unroll
-    for (int j = 0; j < kPer; j++) {
-      v[j] = buf[i * kPer + j];
-      sum += v[j];
-    }
-    const uint32_t incl = wave_incl_scan(sum, lane);
     if (lane == 63) wtot[w] = incl;
     __syncthreads();
-    uint32_t before = 0, total = 0;
+    int64_t before = 0, total = 0;
 #pragma unroll
     for (int k = 0; k < 16; k++) {
-      const uint32_t t = wtot[k];
-      before += k < w ? t : 0u;
+      const int64_t t = wtot[k];
+      before += k < w ? t : 0;
       total += t;
     }
-    int64_t run = carry + before + (incl - sum);
-#pragma unroll
-    for (int j = 0; j < kPer; j++) {
-      const int32_t k = base + i * kPer + j;
-      if (k < ntiles) tile_off[k] = run;
-      run += v[j];
-    }
+    if (c < nchunks) tile_off[(int64_t)c * kScanChunk] = carry + before + (incl - x);
     carry += total;
-    __syncthreads();  // buf and wtot are rewritten by the next chunk
+    __syncthreads();  // wtot is rewritten by the next round
   }
   if (i == 0) tile_off[ntiles] = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_var_scan_chunks(const uint32_t* __restrict__ tile_count,
+                                                          int32_t ntiles,
+                                                          int64_t* __restrict__ tile_off) {
+  __shared__ uint32_t buf[kScanChunk];
+  __shared__ uint32_t wtot[16];
+  __shared__ int64_t chunk_base;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  if (threadIdx.x == 0) chunk_base = tile_off[base];
+  uint32_t v[kScanPer], before, total;
+  scan_chunk_counts(tile_count, ntiles, base, buf, wtot, v, &before, &total);
+  // chunk_base was read before the first barrier inside scan_chunk_counts
+  int64_t run = chunk_base + before;
+#pragma unroll
+  for (int j = 0; j < kScanPer; j++) {
+    const int64_t k = base + threadIdx.x * kScanPer + j;
+    if (k < ntiles) tile_off[k] = run;
+    run += v[j];
+  }
 }
 
 // Copy each tile's words from its staging slot to its offset; words at or
@@ -825,7 +886,7 @@ __global__ void k_var_chunk_offsets(const int64_t* __restrict__ chunk_first, int
 // the workers through a device-memory counter.  Every other wavefront is an
 // independent worker: it walks the device ring in order (cursor = request
 // number), claims 64-block tiles of the request at its cursor with a
-// compare-and-swap on a per-slot counter tagged with the request number (so a
+// fetch-add on a per-slot counter tagged with the request number (so a
 // slot reused for a later request is never confused with the earlier one),
 // codes the tile and counts it done; the wavefront that completes a request's
 // last tile raises the request's completion flag in host memory.  Requests
@@ -1373,7 +1434,14 @@ hipError_t launch_plan_encode_var(const PlanDev& p, bool vec4, const float* src,
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_var_scan, dim3(1), dim3(1024), 0, s, tile_count, ntiles, tile_off);
+  const int32_t nchunks = (int32_t)(((int64_t)ntiles + kScanChunk - 1) / kScanChunk);
+  if (nchunks > 0)
+    hipLaunchKernelGGL(k_var_scan_sums, dim3(nchunks), dim3(1024), 0, s, tile_count, ntiles,
+                       tile_off);
+  hipLaunchKernelGGL(k_var_scan_bases, dim3(1), dim3(1024), 0, s, nchunks, ntiles, tile_off);
+  if (nchunks > 0)
+    hipLaunchKernelGGL(k_var_scan_chunks, dim3(nchunks), dim3(1024), 0, s, tile_count, ntiles,
+                       tile_off);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_var_place, dim3((ntiles + 3) / 4), dim3(256), 0, s, stage, tile_count,
