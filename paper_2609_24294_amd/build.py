@@ -62,6 +62,17 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     return LIB_PATH
 
 
+def build_program(src: str, out: str, verbose: bool = False) -> str:
+    """Compile a standalone HIP program (a measurement probe) with the
+    library's flags."""
+    cmd = [hipcc(), *[f for f in HIPCC_FLAGS if f != "-fPIC"], src, "-o", out + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     print(LIB_PATH)
