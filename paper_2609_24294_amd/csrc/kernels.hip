@@ -1071,7 +1071,12 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
       pub = dev_load(&d.dctl->published);
       if (cursor >= pub) {
         if (dev_load(&d.dctl->stop) || now - t_work > d.idle_ticks) break;
-        __builtin_amdgcn_s_sleep(32);
+        // Idle wavefronts poll the published counter about every 14 us:
+        // a thousand wavefronts polling one word every microsecond slowed
+        // every coherent access of the loop (p50 at a quarter of the plain
+        // form's capacity 48 -> 30 us with the longer sleep), and with that
+        // many pollers at random phases some wake within a microsecond.
+        for (int i = 0; i < 4; i++) __builtin_amdgcn_s_sleep(127);
         continue;
       }
     }
