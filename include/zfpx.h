@@ -395,9 +395,12 @@ int zfpx_graph_destroy(zfpx_graph* graph);
  *                        device loop (0 = 2 per compute unit).  Allocates
  *                        pinned host memory and device memory.
  *   zfpx_server_submit : queue a request; EINVAL if malformed or larger than
- *                        the whole budget, EAGAIN if the queue is full,
+ *                        the whole budget, EAGAIN if the host queue already
+ *                        holds max_queued requests not yet admitted (the
+ *                        request is not taken; submit it again later),
  *                        ESTATE once a server has taken 2^32 - 1 requests.
  *                        Thread-safe.  Returns a ticket.
+ *   zfpx_server_set_max_queue : max_queued in 1 .. 2^20 (default 2^20).
  *   zfpx_server_progress / _poll : collect completions and admit more;
  *                        poll reports done and the latency (seconds from
  *                        submit to the host seeing completion) and forgets
@@ -434,6 +437,7 @@ int zfpx_server_poll(zfpx_server* sv, uint64_t ticket, int* done, double* latenc
 int zfpx_server_drain(zfpx_server* sv, double timeout_s);
 int zfpx_server_stats(zfpx_server* sv, uint64_t* admitted, size_t* max_inflight_bytes,
                       uint64_t* loop_launches);
+int zfpx_server_set_max_queue(zfpx_server* sv, size_t max_queued);
 int zfpx_server_destroy(zfpx_server* sv);
 int zfpx_server_replay(zfpx_server* sv, const zfpx_request* rq, const double* arrival_s,
                        int64_t n, double timeout_s, double* latency_s);

@@ -378,6 +378,13 @@ int zfpx_server_stats(zfpx_server* sv, uint64_t* completed, size_t* max_inflight
   return ZFPX_OK;
 }
 
+int zfpx_server_set_max_queue(zfpx_server* sv, size_t max_queued) {
+  if (!sv || max_queued < 1 || max_queued > ((size_t)1 << 20)) return ZFPX_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  sv->max_queue = max_queued;
+  return ZFPX_OK;
+}
+
 int zfpx_server_destroy(zfpx_server* sv) {
   if (!sv) return ZFPX_EINVAL;
   server_free(sv);

@@ -62,6 +62,7 @@ _SIGS = {
     "zfpx_server_drain": (_INT, [_P, _c.c_double]),
     "zfpx_server_stats": (_INT, [_P, _c.POINTER(_c.c_uint64), _c.POINTER(_SZ),
                                  _c.POINTER(_c.c_uint64)]),
+    "zfpx_server_set_max_queue": (_INT, [_P, _SZ]),
     "zfpx_server_destroy": (_INT, [_P]),
     "zfpx_server_replay": (_INT, [_P, _P, _P, _I64, _c.c_double, _P]),
     "zfpx_plain_replay": (_INT, [_P, _P, _I64, _c.c_double, _P, _P]),
@@ -497,6 +498,9 @@ class Server:
 
     def drain(self, timeout_s: float = 60.0) -> None:
         _check(_lib.zfpx_server_drain(self._h, timeout_s), "zfpx_server_drain")
+
+    def set_max_queue(self, max_queued: int) -> None:
+        _check(_lib.zfpx_server_set_max_queue(self._h, max_queued), "zfpx_server_set_max_queue")
 
     def stats(self):
         a, m, l = _c.c_uint64(), _SZ(), _c.c_uint64()

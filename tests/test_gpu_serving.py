@@ -124,6 +124,47 @@ def test_server_rejects_bad_requests(zfpx_lib):
     sv.close()
 
 
+def test_server_queue_full_is_eagain(zfpx_lib):
+    """The budget holds one 64 MB request, so the others wait in the host
+    queue; with a queue of two, a submit while the queue is full gets EAGAIN
+    and the request is not taken (it can be submitted again later); every
+    request taken completes with the oracle's result."""
+    pool = torch.from_numpy(W.serving_pool(nx_max=32768)).to(DEV)
+    rate = 16
+    ref = _oracle_ref(0, rate, pool)
+    nbytes = pool.numel() * 4 + ref.numel() * 8
+    bufs = [torch.empty_like(ref) for _ in range(8)]
+    torch.cuda.synchronize()
+    sv = zfpx_lib.Server(nbytes, max_slots=4)
+    sv.set_max_queue(2)
+    outs, tickets, rejected = [], [], None
+    for i, out in enumerate(bufs):  # a submit takes microseconds, a 64 MB request far longer
+        rq = zfpx_lib.make_request(0, rate, pool, out, tag=i)
+        try:
+            tickets.append(sv.submit(rq))
+        except zfpx_lib.ZfpxError as e:
+            assert e.status == zfpx_lib.EAGAIN
+            rejected = (rq, out)
+            break
+        outs.append(out)
+    # one in flight and two queued at most when the rejection came
+    assert rejected is not None and len(outs) <= 3
+    sv.drain(60.0)
+    tickets.append(sv.submit(rejected[0]))  # taken now that the queue has room
+    outs.append(rejected[1])
+    sv.drain(60.0)
+    for tk in tickets:
+        done, _ = sv.poll(tk)
+        assert done
+    for pol in (-1, 0, (1 << 20) + 1):
+        with pytest.raises(zfpx_lib.ZfpxError):
+            sv.set_max_queue(pol)
+    sv.close()
+    torch.cuda.synchronize()
+    for o in outs:
+        assert torch.equal(o, ref)
+
+
 def test_replay_forms_agree(zfpx_lib):
     rng = np.random.default_rng(42)
     pool = torch.from_numpy(W.serving_pool(nx_max=4096)).to(DEV)
