@@ -818,7 +818,7 @@ def serving_report(torch, zfpx, W, count, workgroups=0):
     """Poisson arrivals of mixed compress/decompress requests (64 KB .. 64 MB of
     float32, rate 8/16/32): the saturated throughput of the serving loop and
     of one launch per request (every request at t = 0), then p50/p99 latency
-    of both at 25 .. 125% of the plain form's saturated throughput.  At the
+    of both at 25 .. 200% of the plain form's saturated throughput.  At the
     100% point every request writes its own output buffer and each served
     output is compared bit for bit with the same request run alone in one
     launch (stopping at the first mismatch)."""
@@ -885,7 +885,7 @@ def serving_report(torch, zfpx, W, count, workgroups=0):
                    "throughput; request buffers are drawn from 32 rotating sets except at "
                    "load 1.0, where every request has its own output; latency = completion "
                    "seen by the host minus scheduled arrival", "points": []}
-    for load in (0.25, 0.5, 0.75, 0.9, 1.0, 1.25):
+    for load in (0.25, 0.5, 0.75, 0.9, 1.0, 1.25, 1.5, 2.0):
         gap = mean_bytes / (load * sat)
         stream = W.request_stream(count, gap)
         arrival = np.array([q.t_arrive for q in stream])

@@ -86,7 +86,7 @@ struct ServeDesc {   // one admitted request; host-coherent memory, slot = seq %
   int32_t nblocks, ntiles;
   uint32_t vspan;     // float32 array span in bytes when it is 16-byte accessible
                       // within 4 GiB (unit x stride, aligned rows), else 0
-  int32_t per_claim;  // tiles a wavefront takes with one claim (1..8)
+  int32_t per_claim;  // tiles per wavefront of a workgroup's claim (1..8)
   RegularDev geo;
   uint64_t in, out;  // device addresses
 };
@@ -118,7 +118,7 @@ struct ServeDev {        // arguments of the device loop
 };
 
 hipError_t launch_serve(const ServeDev& d, int workgroups, hipStream_t s);
-constexpr int kServeWaves = 2;  // wavefronts per workgroup of the device loop
+constexpr int kServeWaves = 4;  // wavefronts per workgroup of the device loop
 
 // LDS bytes a workgroup of `wg` threads needs at `rate`.
 size_t lds_bytes(int wg, int rate);

@@ -883,14 +883,15 @@ __global__ void k_var_chunk_offsets(const int64_t* __restrict__ chunk_first, int
 // Wavefront 0 of workgroup 0 is the dispatcher: it alone polls the host's
 // control block (over PCIe, with a pause between polls) and copies newly
 // published descriptors into a ring in device memory, then publishes them to
-// the workers through a device-memory counter.  Every other wavefront is an
-// independent worker: it walks the device ring in order (cursor = request
-// number), claims 64-block tiles of the request at its cursor with a
-// fetch-add on a per-slot counter tagged with the request number (so a
-// slot reused for a later request is never confused with the earlier one),
-// codes the tile and counts it done; the wavefront that completes a request's
-// last tile raises the request's completion flag in host memory.  Requests
-// overlap on the device as soon as they are published.  Every wavefront
+// the workers through a device-memory counter.  Every other workgroup is an
+// independent worker: its first wavefront walks the device ring in order
+// (cursor = request number) and claims runs of 64-block tiles of the request
+// at its cursor with a fetch-add on a per-slot counter tagged with the
+// request number (so a slot reused for a later request is never confused
+// with the earlier one); the workgroup's wavefronts code the run's tiles, and
+// the run is counted done; the workgroup that completes a request's last
+// tile raises the request's completion flag in host memory.  Requests
+// overlap on the device as soon as they are published.  Every workgroup
 // leaves when the host asks to stop, after `idle_ticks` without work, or after
 // `max_ticks` in total, so the grid always drains.
 
@@ -1020,77 +1021,54 @@ __device__ __forceinline__ void serve_dispatch(const ServeDev d, int lane, uint6
   }
 }
 
-__global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
-  extern __shared__ uint64_t lds[];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
-  if (blockIdx.x == 0 && wave == 0) {
-    serve_dispatch(d, lane, t_start);
-    return;
-  }
-  uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(32);
-  uint64_t t_work = t_start;
-  uint64_t cursor = sys_load(&d.ctl->oldest);
-  uint64_t pub = 0;
-  // descriptor of the request whose tiles this wavefront last claimed; it
-  // stays valid while the wavefront holds a claimed tile of that request (the
-  // slot is not reused before every tile of the request is done)
+// What wavefront 0 of a worker workgroup hands to the others in LDS: a run
+// of tiles [t0, t1) of request q (slot `slot`), or the order to leave.
+struct ServeRun {
   ServeDesc q;
-  uint32_t qtag = 0;
-  bool have_q = false;
-  // tiles in hand: [t_next, t_end) of request q in slot hslot; `held` of the
-  // run are coded but not yet counted done
-  int32_t t_next = 0, t_end = 0, held = 0, hslot = 0;
+  int32_t t0, t1, slot, leave;
+};
+
+// Wavefront 0 of a worker workgroup: find the workgroup's next run of tiles.
+// It walks the device ring in order (cursor = request number) and claims a
+// run with a fetch-add on the slot's counter, whose high half names the
+// request it counts for.  The run belongs to that request, which is the one
+// at the cursor or (the slot reused after that one finished) a later one,
+// and is processed for it.  A counter still naming an older request is moved
+// on with an atomic max (tags only grow, so the max neither loses a later tag
+// nor fights the fetch-adds of other workgroups); the done counter first, so
+// that no tile of the request can complete before its done counter is reset.
+// Returns false when the workgroup is to leave (stop asked, idle too long, or
+// out of time).
+struct ServeCursor {
+  uint64_t cursor, pub, t_work;
+  uint32_t qtag;
+  bool have_q;
+  ServeDesc q;  // of the last request claimed (valid while have_q)
+};
+
+__device__ __forceinline__ bool serve_find_run(const ServeDev& d, int lane, uint64_t t_start,
+                                               ServeCursor& c, int32_t& t0, int32_t& t1,
+                                               int32_t& slot_out) {
   for (;;) {
-    if (t_next < t_end) {
-      serve_tile(q, opaque(lane), wlds, t_next);
-      wave_sync_lds();
-      t_next++;
-      held++;
-      if (t_next == t_end) {
-        // the run's output was written through to memory (system-coherent
-        // stores); wait until every store has completed before counting the
-        // run done, so no cache write-back is needed
-        wait_memory();
-        if (lane == 0) {
-          const uint64_t prev = __hip_atomic_fetch_add(d.done + hslot, (uint64_t)held,
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if ((int32_t)(uint32_t)prev + held == q.ntiles)
-            __hip_atomic_store(d.done_flag + hslot, q.seq + 1, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-        held = 0;
-        t_work = __builtin_amdgcn_s_memrealtime();
-      }
-      continue;
-    }
     const uint64_t now = __builtin_amdgcn_s_memrealtime();
-    if (now - t_start > d.max_ticks) break;
-    if (cursor >= pub) {
-      pub = dev_load(&d.dctl->published);
-      if (cursor >= pub) {
-        if (dev_load(&d.dctl->stop) || now - t_work > d.idle_ticks) break;
-        // Idle wavefronts poll the published counter about every 14 us:
-        // a thousand wavefronts polling one word every microsecond slowed
-        // every coherent access of the loop (p50 at a quarter of the plain
-        // form's capacity 48 -> 30 us with the longer sleep), and with that
-        // many pollers at random phases some wake within a microsecond.
+    if (now - t_start > d.max_ticks) return false;
+    if (c.cursor >= c.pub) {
+      c.pub = dev_load(&d.dctl->published);
+      if (c.cursor >= c.pub) {
+        if (dev_load(&d.dctl->stop) || now - c.t_work > d.idle_ticks) return false;
+        // Idle workgroups poll the published counter about every 14 us: many
+        // pollers of one word every microsecond slow every coherent access of
+        // the loop, and with hundreds of pollers at random phases some wake
+        // within a microsecond.
         for (int i = 0; i < 4; i++) __builtin_amdgcn_s_sleep(127);
         continue;
       }
     }
-    const int slot = (int)(cursor % (uint64_t)d.cap);
-    const uint32_t want = (uint32_t)cursor;
-    const int32_t take = have_q && qtag == want ? q.per_claim : 1;
-    // claim a run of tiles (lane 0): a fetch-add on the slot's counter, whose
-    // high half names the request it counts for.  The run belongs to that
-    // request, which is this one or (the slot reused after this one finished)
-    // a later one, and is processed for it.  A counter still naming an older
-    // request is moved on to this one with an atomic max (tags only grow, so
-    // the max neither loses a later tag nor fights the fetch-adds of other
-    // wavefronts); the done counter first, so that no tile of this request
-    // can complete before its done counter is reset.
+    const int slot = (int)(c.cursor % (uint64_t)d.cap);
+    const uint32_t want = (uint32_t)c.cursor;
+    // one run per wavefront of the workgroup; before the descriptor is known,
+    // one tile per wavefront
+    const int32_t take = kServeWaves * (c.have_q && c.qtag == want ? c.q.per_claim : 1);
     uint64_t got = 0;  // (request tag << 32) | first tile
     if (lane == 0) {
       for (;;) {
@@ -1112,13 +1090,14 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
     got = __shfl(got, 0, 64);
     const uint32_t gtag = (uint32_t)(got >> 32);
     const int32_t tile = (int32_t)(uint32_t)got;
-    if (!have_q || qtag != gtag) {
+    if (!c.have_q || c.qtag != gtag) {
       const ServeDesc* r = d.ring_dev + slot;
       // coherent vector loads, kept in scalar registers (every lane read the
       // same words).  seq is read before and after the other words: if the
       // claimed request has completed, the dispatcher may be rewriting the
       // slot for a later one, and only a descriptor whose seq did not change
       // across the reads is whole.
+      ServeDesc& q = c.q;
       const uint64_t seq0 = uniform64(dev_load(&r->seq));
       wait_memory();
       q.ntiles = __builtin_amdgcn_readfirstlane(dev_load32(&r->ntiles));
@@ -1140,25 +1119,113 @@ __global__ __launch_bounds__(64 * kServeWaves) void k_serve(ServeDev d) {
       q.out = uniform64(dev_load(&r->out));
       wait_memory();
       q.seq = uniform64(dev_load(&r->seq));
-      qtag = gtag;
-      have_q = q.seq == seq0 && (uint32_t)q.seq == gtag;
-      if (!have_q) {
+      c.qtag = gtag;
+      c.have_q = q.seq == seq0 && (uint32_t)q.seq == gtag;
+      if (!c.have_q) {
         // the claimed request finished and the slot holds (or is being
         // rewritten for) a later one whose claim counter is not moved on
         // yet: nothing to do here
-        cursor++;
+        c.cursor++;
         continue;
       }
     }
-    if (tile >= q.ntiles) {
+    if (tile >= c.q.ntiles) {
       // every tile of the slot's request is claimed (and the cursor's request
       // with it): move on
-      cursor++;
+      c.cursor++;
       continue;
     }
-    t_next = tile;
-    t_end = q.ntiles - tile < take ? q.ntiles : tile + take;
-    hslot = slot;
+    t0 = tile;
+    t1 = c.q.ntiles - tile < take ? c.q.ntiles : tile + take;
+    slot_out = slot;
+    return true;
+  }
+}
+
+// Workgroup 0's first wavefront is the dispatcher (the workgroup takes no
+// tiles and meets no barrier).  Every other workgroup is a worker: its first
+// wavefront finds a run of tiles for the whole workgroup and hands it over in
+// LDS; each wavefront codes every kServeWaves-th tile of the run; after a
+// barrier the first wavefront counts the run done.  Claims per workgroup, not
+// per wavefront, keep the claim and descriptor traffic of walking every
+// request at one claimer per workgroup while two wavefronts per SIMD share
+// the coding.
+__global__ __launch_bounds__(64 * kServeWaves) __attribute__((amdgpu_waves_per_eu(2)))
+void k_serve(ServeDev d) {
+  extern __shared__ uint64_t lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+  if (blockIdx.x == 0) {
+    if (wave == 0) serve_dispatch(d, lane, t_start);
+    return;
+  }
+  uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(32);
+  ServeRun* run = reinterpret_cast<ServeRun*>(lds + (size_t)kServeWaves * 64 * lds_stride(32));
+  ServeCursor c;
+  c.cursor = sys_load(&d.ctl->oldest);
+  c.pub = 0;
+  c.t_work = t_start;
+  c.qtag = 0;
+  c.have_q = false;
+  for (;;) {
+    if (wave == 0) {
+      int32_t t0 = 0, t1 = 0, slot = 0;
+      const bool go = serve_find_run(d, lane, t_start, c, t0, t1, slot);
+      if (lane == 0) {
+        run->leave = go ? 0 : 1;
+        if (go) {
+          run->q = c.q;
+          run->t0 = t0;
+          run->t1 = t1;
+          run->slot = slot;
+        }
+      }
+    }
+    __syncthreads();  // the run is in LDS
+    if (__builtin_amdgcn_readfirstlane(run->leave)) break;
+    ServeDesc q;
+    q.seq = uniform64(run->q.seq);
+    q.op = __builtin_amdgcn_readfirstlane(run->q.op);
+    q.rate = __builtin_amdgcn_readfirstlane(run->q.rate);
+    q.nblocks = __builtin_amdgcn_readfirstlane(run->q.nblocks);
+    q.ntiles = __builtin_amdgcn_readfirstlane(run->q.ntiles);
+    q.vspan = (uint32_t)__builtin_amdgcn_readfirstlane(run->q.vspan);
+    q.per_claim = 0;
+    q.geo.nx = (int64_t)uniform64((uint64_t)run->q.geo.nx);
+    q.geo.ny = (int64_t)uniform64((uint64_t)run->q.geo.ny);
+    q.geo.nz = (int64_t)uniform64((uint64_t)run->q.geo.nz);
+    q.geo.sx = (int64_t)uniform64((uint64_t)run->q.geo.sx);
+    q.geo.sy = (int64_t)uniform64((uint64_t)run->q.geo.sy);
+    q.geo.sz = (int64_t)uniform64((uint64_t)run->q.geo.sz);
+    q.geo.nbx = __builtin_amdgcn_readfirstlane(run->q.geo.nbx);
+    q.geo.nby = __builtin_amdgcn_readfirstlane(run->q.geo.nby);
+    q.in = uniform64(run->q.in);
+    q.out = uniform64(run->q.out);
+    const int32_t t0 = __builtin_amdgcn_readfirstlane(run->t0);
+    const int32_t t1 = __builtin_amdgcn_readfirstlane(run->t1);
+    const int32_t slot = __builtin_amdgcn_readfirstlane(run->slot);
+    for (int32_t t = t0 + wave; t < t1; t += kServeWaves) {
+      serve_tile(q, opaque(lane), wlds, t);
+      wave_sync_lds();
+    }
+    // the tiles' output was written through to memory (system-coherent
+    // stores): every wavefront waits until its stores have completed, and
+    // after the barrier (which also frees the run record for the next
+    // write) the run is counted done, so no cache write-back is needed
+    wait_memory();
+    __syncthreads();
+    if (wave == 0) {
+      if (lane == 0) {
+        const int32_t n = t1 - t0;
+        const uint64_t prev = __hip_atomic_fetch_add(d.done + slot, (uint64_t)n,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int32_t)(uint32_t)prev + n == q.ntiles)
+          __hip_atomic_store(d.done_flag + slot, q.seq + 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      c.t_work = __builtin_amdgcn_s_memrealtime();
+    }
   }
 }
 
@@ -1357,7 +1424,7 @@ static unsigned covering_grid(size_t work) {
 }
 
 hipError_t launch_serve(const ServeDev& d, int workgroups, hipStream_t s) {
-  size_t shm = (size_t)kServeWaves * 64 * lds_stride(32) * sizeof(uint64_t);
+  size_t shm = (size_t)kServeWaves * 64 * lds_stride(32) * sizeof(uint64_t) + sizeof(ServeRun);
   hipLaunchKernelGGL(k_serve, dim3(workgroups > 0 ? workgroups : 1), dim3(64 * kServeWaves), shm,
                      s, d);
   return hipGetLastError();

@@ -206,15 +206,15 @@ static int progress_locked(zfpx_server* sv) {
     q.nblocks = (int32_t)p.nblocks;
     q.ntiles = (int32_t)((p.nblocks + 63) / 64);
     q.vspan = vector_span(&p.rq);
-    // Tiles are handed out in runs of up to 8 per claim, by load: with k
-    // requests in flight a request's fair share of the W worker wavefronts is
-    // about W / k, and runs of ntiles * k / (2 W) tiles give it that many
-    // claims' worth of spread.  A lone request is spread one tile per claim
-    // over every wavefront (lowest latency); under load, longer runs cut
-    // claim and descriptor traffic (saturated throughput 581 -> 689 GB/s of
-    // float32 on the request mix of the benchmark).
+    // Tiles are handed out in runs of up to 8 per wavefront per claim (a
+    // worker workgroup claims one run for each of its wavefronts), by load:
+    // with k requests in flight a request's fair share of the W worker
+    // wavefronts is about W / k, and runs of ntiles * k / (2 W) tiles give it
+    // that many claims' worth of spread.  A lone request is spread one tile
+    // per wavefront over every workgroup (lowest latency); under load, longer
+    // runs cut claim and descriptor traffic.
     {
-      const int64_t workers = std::max<int64_t>(1, (int64_t)sv->workgroups * kServeWaves - 1);
+      const int64_t workers = std::max<int64_t>(1, (int64_t)(sv->workgroups - 1) * kServeWaves);
       const int64_t run = (int64_t)q.ntiles * (int64_t)(sv->nactive + 1) / (2 * workers);
       q.per_claim = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, run));
     }
@@ -259,9 +259,9 @@ int zfpx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t workg
     delete sv;
     return ZFPX_EHIP;
   }
-  // two workgroups (four wavefronts) per compute unit: more wavefronts only
-  // add contention on the claim counters
-  sv->workgroups = workgroups > 0 ? workgroups : device_cu_count() * 2;
+  // two workgroups of four wavefronts per compute unit (two wavefronts per
+  // SIMD); workgroup 0 only dispatches, so at least one more is needed
+  sv->workgroups = workgroups > 0 ? std::max(2, workgroups) : device_cu_count() * 2;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, sv->device) != hipSuccess ||
       khz <= 0)
