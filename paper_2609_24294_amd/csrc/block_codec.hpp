@@ -215,6 +215,20 @@ ZFPX_HD uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
 #endif
 }
 
+// Any three-input bitwise function in one instruction: bit i of TT is the
+// result for the inputs (s0, s1, s2) = (bit 2, bit 1, bit 0 of i).
+template <uint32_t TT>
+ZFPX_HD uint32_t bitop3(uint32_t s0, uint32_t s1, uint32_t s2) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(s0, s1, s2, TT);
+#else
+  uint32_t r = 0;
+  for (int i = 0; i < 8; i++)
+    if ((TT >> i) & 1) r |= ((i & 4) ? s0 : ~s0) & ((i & 2) ? s1 : ~s1) & ((i & 1) ? s2 : ~s2);
+  return r;
+#endif
+}
+
 // INV_HI complements the rows r + J written by the stage (the odd rows when
 // J = 1), at no cost.
 template <int J, uint32_t MASK, bool INV_HI = false>
@@ -234,6 +248,22 @@ ZFPX_HD void transpose_bits64(uint64_t* a) {
   }
 }
 
+// The J = 1 stage reading the odd rows complemented (the input rows r + 1),
+// at no cost: each output is one three-input function of the two rows.
+ZFPX_HD void transpose_bits64_odd_in_inverted(uint64_t* a) {
+  constexpr uint32_t M = 0x55555555u, HM = M << 1;
+#pragma unroll
+  for (int r = 0; r < 32; r += 2) {
+    uint32_t xl = (uint32_t)a[r], xh = (uint32_t)(a[r] >> 32);
+    uint32_t yl = (uint32_t)a[r + 1], yh = (uint32_t)(a[r + 1] >> 32);
+    // odd row: (M & x >> 1) | (~M & ~y); even row: (HM & ~(y << 1)) | (~HM & x)
+    a[r + 1] = (uint64_t)bitop3<0xC5>(M, xl >> 1, yl) | ((uint64_t)bitop3<0xC5>(M, xh >> 1, yh) << 32);
+    a[r] = (uint64_t)bitop3<0x3A>(HM, yl << 1, xl) | ((uint64_t)bitop3<0x3A>(HM, yh << 1, xh) << 32);
+  }
+}
+
+// Each stage swaps one bit of the row index with the same bit of the column
+// index; the stages commute, so any order gives the transpose.
 // INVERT_ODD: afterwards rows 1, 3, ..., 31 are complemented.  XOR with a
 // constant commutes with the transpose, so the encoder's negabinary XOR with
 // 0xaaaaaaaa (bits 1, 3, ..., 31 of every coefficient) becomes exactly this.
@@ -244,6 +274,17 @@ ZFPX_HD void transpose32x2(uint64_t* a) {
   transpose_bits64<4, 0x0f0f0f0fu>(a);
   transpose_bits64<2, 0x33333333u>(a);
   transpose_bits64<1, 0x55555555u, INVERT_ODD>(a);
+}
+
+// The transpose of rows 1, 3, ..., 31 complemented (the J = 1 stage first,
+// reading them inverted): for the decoder, whose odd bit planes are the
+// complemented ones (the negabinary XOR with 0xaaaaaaaa seen plane-wise).
+ZFPX_HD void transpose32x2_odd_in_inverted(uint64_t* a) {
+  transpose_bits64_odd_in_inverted(a);
+  transpose_bits64<2, 0x33333333u>(a);
+  transpose_bits64<4, 0x0f0f0f0fu>(a);
+  transpose_bytes64<8>(a);
+  transpose_bytes64<16>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -404,7 +445,8 @@ ZFPX_HD uint32_t encode_block(float* v, uint64_t* out, int rate_rt, int maxprec 
             if (e == 0) break;
             sp += e << t;
           }
-          const uint64_t code = 1 | (sp << 1) | ((sp ^ (uint64_t(1) << hs)) << 2);
+          // the three parts share no bit, so adds join them (shift-adds)
+          const uint64_t code = ((sp ^ (uint64_t(1) << hs)) << 2) + ((sp << 1) + 1);
           or_bits(out, pos, code);
           pos += (uint32_t)hs + 2;
           n += hy + 1;
@@ -553,11 +595,11 @@ ZFPX_HD void decode_block(const uint64_t* in, float* vout, int rate_rt, int maxp
       }
       if (pos > maxbits) pos = maxbits;
     }
-    // odd planes complemented: after the transpose every coefficient is
-    // then XORed with the negabinary mask 0xaaaaaaaa (bits 1, 3, ..., 31)
-    X[k] = (k & 1) ? ~x : x;
+    X[k] = x;
   }
-  transpose32x2(X);
+  // odd planes complemented as the transpose reads them: every coefficient
+  // comes out XORed with the negabinary mask 0xaaaaaaaa (bits 1, 3, ..., 31)
+  transpose32x2_odd_in_inverted(X);
   int32_t q[64];
 #pragma unroll
   for (int s = 0; s < 32; s++) {

@@ -1053,7 +1053,12 @@ __device__ __forceinline__ bool serve_find_run(const ServeDev& d, int lane, uint
     const uint64_t now = __builtin_amdgcn_s_memrealtime();
     if (now - t_start > d.max_ticks) return false;
     if (c.cursor >= c.pub) {
-      c.pub = dev_load(&d.dctl->published);
+      // idle means nothing published for idle_ticks, not no work for this
+      // workgroup: otherwise workgroups that small requests leave without
+      // tiles would leave, and a large request find the loop thinned out
+      const uint64_t p = dev_load(&d.dctl->published);
+      if (p != c.pub) c.t_work = now;
+      c.pub = p;
       if (c.cursor >= c.pub) {
         if (dev_load(&d.dctl->stop) || now - c.t_work > d.idle_ticks) return false;
         // Idle workgroups poll the published counter about every 14 us: many

@@ -50,6 +50,7 @@ struct SlotState {
   uint64_t seq = 0;
   uint64_t ticket = 0;
   size_t bytes = 0;
+  int64_t ntiles = 0;
   double t_submit = 0;
 };
 
@@ -113,6 +114,7 @@ struct zfpx_server {
   // requests low_seq .. next_seq-1 may be in flight (at most cap of them)
   uint64_t low_seq = 0;
   size_t nactive = 0;
+  int64_t inflight_tiles = 0;  // tiles of the requests in flight
   double last_query = 0;  // last time the device loop's end was queried
   // tickets completed since the last look, gathered while collect_done is set
   bool collect_done = false;
@@ -183,6 +185,7 @@ static int progress_locked(zfpx_server* sv) {
       s.active = false;
       sv->nactive--;
       sv->inflight -= s.bytes;
+      sv->inflight_tiles -= s.ntiles;
       Result& r = sv->results[s.ticket];
       r.done = true;
       r.latency = t - s.t_submit;
@@ -210,12 +213,16 @@ static int progress_locked(zfpx_server* sv) {
     // worker workgroup claims one run for each of its wavefronts), by load:
     // with k requests in flight a request's fair share of the W worker
     // wavefronts is about W / k, and runs of ntiles * k / (2 W) tiles give it
-    // that many claims' worth of spread.  A lone request is spread one tile
-    // per wavefront over every workgroup (lowest latency); under load, longer
-    // runs cut claim and descriptor traffic.
+    // that many claims' worth of spread; but a share by tiles is what counts
+    // when the others are small, so the run is also at most T / (2 W), T the
+    // tiles in flight with this request's.  A lone request is spread one
+    // tile per wavefront over every workgroup (lowest latency); under load,
+    // longer runs cut claim and descriptor traffic.
     {
       const int64_t workers = std::max<int64_t>(1, (int64_t)(sv->workgroups - 1) * kServeWaves);
-      const int64_t run = (int64_t)q.ntiles * (int64_t)(sv->nactive + 1) / (2 * workers);
+      const int64_t by_count = (int64_t)q.ntiles * (int64_t)(sv->nactive + 1) / (2 * workers);
+      const int64_t by_tiles = (sv->inflight_tiles + q.ntiles) / (2 * workers);
+      const int64_t run = std::min(by_count, by_tiles);
       q.per_claim = (int32_t)std::min<int64_t>(8, std::max<int64_t>(1, run));
     }
     q.geo = RegularDev{p.rq.nx, p.rq.ny, p.rq.nz, p.rq.sx, p.rq.sy, p.rq.sz,
@@ -229,8 +236,10 @@ static int progress_locked(zfpx_server* sv) {
     s.seq = q.seq;
     s.ticket = p.ticket;
     s.bytes = p.bytes;
+    s.ntiles = q.ntiles;
     s.t_submit = p.t_submit;
     sv->inflight += p.bytes;
+    sv->inflight_tiles += q.ntiles;
     if (sv->inflight > sv->max_inflight) sv->max_inflight = sv->inflight;
     if (q.seq < oldest) oldest = q.seq;
     sv->next_seq++;
