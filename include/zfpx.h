@@ -392,7 +392,7 @@ int zfpx_graph_destroy(zfpx_graph* graph);
  * flight.  Results are bit-identical to the one-request launch form.
  *
  *   zfpx_server_create : max_slots ring entries (1..65536); workgroups of the
- *                        device loop (0 = 2 per compute unit; at least 2 are
+ *                        device loop (0 = 1 per compute unit; at least 2 are
  *                        launched, workgroup 0 only dispatches).  Allocates
  *                        pinned host memory and device memory.
  *   zfpx_server_submit : queue a request; EINVAL if malformed or larger than

@@ -118,7 +118,7 @@ struct ServeDev {        // arguments of the device loop
 };
 
 hipError_t launch_serve(const ServeDev& d, int workgroups, hipStream_t s);
-constexpr int kServeWaves = 4;  // wavefronts per workgroup of the device loop
+constexpr int kServeWaves = 8;  // wavefronts per workgroup of the device loop
 
 // LDS bytes a workgroup of `wg` threads needs at `rate`.
 size_t lds_bytes(int wg, int rate);

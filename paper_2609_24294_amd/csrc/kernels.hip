@@ -1153,8 +1153,8 @@ __device__ __forceinline__ bool serve_find_run(const ServeDev& d, int lane, uint
 // LDS; each wavefront codes every kServeWaves-th tile of the run; after a
 // barrier the first wavefront counts the run done.  Claims per workgroup, not
 // per wavefront, keep the claim and descriptor traffic of walking every
-// request at one claimer per workgroup while two wavefronts per SIMD share
-// the coding.
+// request at one claimer per workgroup (one per compute unit) while two
+// wavefronts per SIMD share the coding.
 __global__ __launch_bounds__(64 * kServeWaves) __attribute__((amdgpu_waves_per_eu(2)))
 void k_serve(ServeDev d) {
   extern __shared__ uint64_t lds[];

@@ -268,9 +268,10 @@ int zfpx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t workg
     delete sv;
     return ZFPX_EHIP;
   }
-  // two workgroups of four wavefronts per compute unit (two wavefronts per
-  // SIMD); workgroup 0 only dispatches, so at least one more is needed
-  sv->workgroups = workgroups > 0 ? std::max(2, workgroups) : device_cu_count() * 2;
+  // one workgroup of eight wavefronts per compute unit (two wavefronts per
+  // SIMD, as many as the LDS slices of rate-32 tiles allow); workgroup 0 only
+  // dispatches, so at least one more is needed
+  sv->workgroups = workgroups > 0 ? std::max(2, workgroups) : device_cu_count();
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, sv->device) != hipSuccess ||
       khz <= 0)
