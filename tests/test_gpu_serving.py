@@ -90,6 +90,25 @@ def test_server_mix_equals_alone(zfpx_lib):
     _check(outs, refs)
 
 
+def test_server_few_workgroups(zfpx_lib):
+    """The smallest loops: 1 (raised to 2: workgroup 0 only dispatches, so one
+    worker) and 3 workgroups code every tile of a mix, each equal to the
+    oracle's."""
+    rng = np.random.default_rng(43)
+    pool = torch.from_numpy(W.serving_pool(nx_max=8192)).to(DEV)
+    for wg in (1, 3):
+        reqs, outs, refs = _requests(zfpx_lib, pool, rng, 20)
+        sv = zfpx_lib.Server(64 << 30, max_slots=8, workgroups=wg)
+        for rq in reqs:
+            sv.submit(rq)
+        sv.drain(60.0)
+        st = sv.stats()
+        sv.close()
+        torch.cuda.synchronize()
+        assert st["admitted"] == len(reqs)
+        _check(outs, refs)
+
+
 def test_server_budget_admission(zfpx_lib):
     rng = np.random.default_rng(41)
     pool = torch.from_numpy(W.serving_pool(nx_max=8192)).to(DEV)
