@@ -402,6 +402,12 @@ int zfpx_graph_destroy(zfpx_graph* graph);
  *                        ESTATE once a server has taken 2^32 - 1 requests.
  *                        Thread-safe.  Returns a ticket.
  *   zfpx_server_set_max_queue : max_queued in 1 .. 2^20 (default 2^20).
+ *   zfpx_server_set_idle_us : the device loop leaves after this long in which
+ *                        no request was published (100 us .. 10 s, default
+ *                        2000); taken at the loop's next launch.  A request
+ *                        that finds the loop gone pays for a new launch
+ *                        (about 0.2 ms on MI355X), while a running loop holds
+ *                        most of every compute unit's LDS.
  *   zfpx_server_progress / _poll : collect completions and admit more;
  *                        poll reports done and the latency (seconds from
  *                        submit to the host seeing completion) and forgets
@@ -439,6 +445,7 @@ int zfpx_server_drain(zfpx_server* sv, double timeout_s);
 int zfpx_server_stats(zfpx_server* sv, uint64_t* admitted, size_t* max_inflight_bytes,
                       uint64_t* loop_launches);
 int zfpx_server_set_max_queue(zfpx_server* sv, size_t max_queued);
+int zfpx_server_set_idle_us(zfpx_server* sv, uint64_t idle_us);
 int zfpx_server_destroy(zfpx_server* sv);
 int zfpx_server_replay(zfpx_server* sv, const zfpx_request* rq, const double* arrival_s,
                        int64_t n, double timeout_s, double* latency_s);

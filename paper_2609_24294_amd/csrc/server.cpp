@@ -120,6 +120,7 @@ struct zfpx_server {
   bool collect_done = false;
   std::vector<uint64_t> completed;
   uint64_t idle_ticks = 0, max_ticks = 0;
+  uint64_t ticks_per_ms = 0;  // device wall clock
   int device = 0;
 };
 
@@ -276,7 +277,8 @@ int zfpx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t workg
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, sv->device) != hipSuccess ||
       khz <= 0)
     khz = 100000;  // 100 MHz
-  sv->idle_ticks = (uint64_t)khz * 2;         // 2 ms without work
+  sv->ticks_per_ms = (uint64_t)khz;
+  sv->idle_ticks = (uint64_t)khz * 2;         // 2 ms in which nothing is published
   sv->max_ticks = (uint64_t)khz * 1000 * 60;  // 60 s per launch at most
   unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
   if (hipHostMalloc((void**)&sv->ctl, sizeof(ServeCtl), fl) != hipSuccess ||
@@ -392,6 +394,14 @@ int zfpx_server_set_max_queue(zfpx_server* sv, size_t max_queued) {
   if (!sv || max_queued < 1 || max_queued > ((size_t)1 << 20)) return ZFPX_EINVAL;
   std::lock_guard<std::mutex> g(sv->mu);
   sv->max_queue = max_queued;
+  return ZFPX_OK;
+}
+
+int zfpx_server_set_idle_us(zfpx_server* sv, uint64_t idle_us) {
+  if (!sv || idle_us < 100 || idle_us > 10000000) return ZFPX_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  // taken by the next launch of the loop
+  sv->idle_ticks = idle_us * sv->ticks_per_ms / 1000;
   return ZFPX_OK;
 }
 

@@ -63,6 +63,7 @@ _SIGS = {
     "zfpx_server_stats": (_INT, [_P, _c.POINTER(_c.c_uint64), _c.POINTER(_SZ),
                                  _c.POINTER(_c.c_uint64)]),
     "zfpx_server_set_max_queue": (_INT, [_P, _SZ]),
+    "zfpx_server_set_idle_us": (_INT, [_P, _c.c_uint64]),
     "zfpx_server_destroy": (_INT, [_P]),
     "zfpx_server_replay": (_INT, [_P, _P, _P, _I64, _c.c_double, _P]),
     "zfpx_plain_replay": (_INT, [_P, _P, _I64, _c.c_double, _P, _P]),
@@ -501,6 +502,9 @@ class Server:
 
     def set_max_queue(self, max_queued: int) -> None:
         _check(_lib.zfpx_server_set_max_queue(self._h, max_queued), "zfpx_server_set_max_queue")
+
+    def set_idle_us(self, idle_us: int) -> None:
+        _check(_lib.zfpx_server_set_idle_us(self._h, idle_us), "zfpx_server_set_idle_us")
 
     def stats(self):
         a, m, l = _c.c_uint64(), _SZ(), _c.c_uint64()

@@ -184,6 +184,38 @@ def test_server_queue_full_is_eagain(zfpx_lib):
         assert torch.equal(o, ref)
 
 
+def test_server_idle_setting(zfpx_lib):
+    """Requests 5 ms apart: with the default 2 ms idle spell the loop leaves
+    and is launched again for each; with a 50 ms spell one launch serves all.
+    Out-of-range settings are rejected; outputs equal the oracle's."""
+    pool = torch.from_numpy(W.serving_pool(nx_max=512)).to(DEV)
+    view = pool[:, :, :256]
+    ref = _oracle_ref(0, 16, view)
+    arrival = np.arange(6) * 5e-3
+    launches = {}
+    for idle in (None, 50000):
+        outs = [torch.empty_like(ref) for _ in arrival]
+        torch.cuda.synchronize()
+        reqs = [zfpx_lib.make_request(0, 16, view, o) for o in outs]
+        sv = zfpx_lib.Server(64 << 30, max_slots=8)
+        try:
+            if idle is not None:
+                sv.set_idle_us(idle)
+            lat = sv.replay(reqs, arrival, timeout_s=30.0)
+            launches[idle] = sv.stats()["loop_launches"]
+            for bad in (0, 99, 10000001):
+                with pytest.raises(RuntimeError):
+                    sv.set_idle_us(bad)
+        finally:
+            sv.close()
+        torch.cuda.synchronize()
+        assert (lat > 0).all()
+        for o in outs:
+            assert _same(o, ref)
+    assert launches[None] == len(arrival)
+    assert launches[50000] == 1
+
+
 def test_replay_forms_agree(zfpx_lib):
     rng = np.random.default_rng(42)
     pool = torch.from_numpy(W.serving_pool(nx_max=4096)).to(DEV)
