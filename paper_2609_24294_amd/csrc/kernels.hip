@@ -564,9 +564,25 @@ __global__ __launch_bounds__(256) void k_encode(Geo geo, const float* __restrict
   }
 }
 
-// The decoder is latency bound (a serial chain of LDS reads through each
-// block's planes): a fourth wavefront per SIMD pays for the few registers
-// this spills.
+// Workgroup i runs on XCD i % 8 (dispatch is round-robin over the XCDs).
+// Renumbered in groups of 64, each XCD takes 8 consecutive workgroups of a
+// group: neighbouring tiles, which share the cache lines at their ends, then
+// mostly meet in one L2 (merged there instead of written back in parts from
+// two), while all XCDs stay in one region of the buffer.  A partial last
+// group keeps its order.  A bijection on [0, n).
+__device__ __forceinline__ int32_t xcd_grouped(uint32_t i, uint32_t n) {
+  constexpr uint32_t kXcds = 8, kRun = 8, kGroup = kXcds * kRun;
+  if (i >= n / kGroup * kGroup) return (int32_t)i;
+  const uint32_t x = i % kXcds, k = i / kXcds;
+  return (int32_t)((k / kRun) * kGroup + x * kRun + k % kRun);
+}
+
+// The decoder's time is that of its writes (16 rows of 1 KB per tile): a
+// fourth wavefront per SIMD pays for the few registers it spills (three per
+// SIMD are slower), and its tiles are taken in XCD-grouped order, so that the
+// cache lines shared by neighbouring tiles are merged in one L2 rather than
+// written back in parts from two (the encoder, bound by instruction issue,
+// gains nothing from the order).
 template <int RATE, bool VEC4, bool PERSIST, class Geo>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_decode(Geo geo, const uint64_t* __restrict__ in,
                                                 float* __restrict__ dst, int rate_rt,
@@ -578,7 +594,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int waves = blockDim.x >> 6;
   uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(rate);
   const int32_t ntiles = tiles_of(b_end - b_begin);
-  int32_t t = blockIdx.x * waves + wave;
+  int32_t t = (PERSIST ? (int32_t)blockIdx.x : xcd_grouped(blockIdx.x, gridDim.x)) * waves + wave;
   if (t >= ntiles) return;
   for (;;) {
     const int32_t b0 = b_begin + (t << 6);
@@ -821,7 +837,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int waves = blockDim.x >> 6;
   uint64_t* slice = lds + (size_t)(wave * 64 + lane) * stride;
   const int32_t ntiles = tiles_of(nblocks);
-  const int32_t t = blockIdx.x * waves + wave;
+  const int32_t t = xcd_grouped(blockIdx.x, gridDim.x) * waves + wave;
   if (t >= ntiles) return;
   const int32_t b0 = t << 6;
   const int nact = nblocks - b0 < 64 ? nblocks - b0 : 64;
