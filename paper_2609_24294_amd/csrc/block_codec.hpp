@@ -297,8 +297,18 @@ ZFPX_HD void transpose32x2_odd_in_inverted(uint64_t* a) {
 constexpr int kSlackWords = 2;
 
 // OR the (up to 64-bit) value `code` into the slice at bit position `pos`.
+// The word index of bit position pos, kept opaque so that the address
+// becomes one shift-add of it (not a shift, a mask and an add).
+ZFPX_HD uint32_t word_of(uint32_t pos) {
+  uint32_t w = pos >> 6;
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm("" : "+v"(w));
+#endif
+  return w;
+}
+
 ZFPX_HD void or_bits(uint64_t* s, uint32_t pos, uint64_t code) {
-  uint32_t w = pos >> 6, b = pos & 63;
+  uint32_t w = word_of(pos), b = pos & 63;
   uint64_t lo = code << b;
   uint64_t hi = (code >> 1) >> (63 - b);
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -322,8 +332,16 @@ ZFPX_HD uint32_t funnel32(uint32_t hi, uint32_t lo, uint32_t b) {
   return (uint32_t)((((uint64_t)hi << 32) | lo) >> (b & 31));
 #endif
 }
+// The 32-bit word index of bit position pos, opaque as word_of.
+ZFPX_HD uint32_t word32_of(uint32_t pos) {
+  uint32_t w = pos >> 5;
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm("" : "+v"(w));
+#endif
+  return w;
+}
 ZFPX_HD uint64_t window64(const uint64_t* s, uint32_t pos) {
-  const u32_alias* d = reinterpret_cast<const u32_alias*>(s) + (pos >> 5);
+  const u32_alias* d = reinterpret_cast<const u32_alias*>(s) + word32_of(pos);
   const uint32_t d0 = d[0], d1 = d[1], d2 = d[2];
   return (uint64_t)funnel32(d1, d0, pos) | ((uint64_t)funnel32(d2, d1, pos) << 32);
 }
@@ -333,7 +351,7 @@ struct Words3 {
   uint32_t w0, w1, w2;
 };
 ZFPX_HD Words3 window_words(const uint64_t* s, uint32_t pos) {
-  const u32_alias* d = reinterpret_cast<const u32_alias*>(s) + (pos >> 5);
+  const u32_alias* d = reinterpret_cast<const u32_alias*>(s) + word32_of(pos);
   return Words3{d[0], d[1], d[2]};
 }
 ZFPX_HD uint64_t window_of(const Words3& w, uint32_t pos) {
@@ -419,7 +437,8 @@ ZFPX_HD uint32_t encode_block(float* v, uint64_t* out, int rate_rt, int maxprec 
       const uint64_t x = X[k];
       or_bits(out, pos, x & vm);  // the first n bits verbatim
       pos += n;
-      if ((x & ~vm) != 0 && pos < maxbits) {
+      // a bit at or above n (vm = 2^n - 1 with every bit below n set)
+      if (x > vm && pos < maxbits) {
         uint64_t y = x >> n;  // bits not yet significant (n < 64 here)
         // Each newly significant coefficient costs a group test 1, the zeros
         // up to it and its own 1 (that one is implied, and not written, for
