@@ -314,7 +314,8 @@ __device__ __forceinline__ void gather_run(const float* __restrict__ src, const 
 #pragma unroll
       for (int dy = 0; dy < 4; dy++) {
         const float* row = src + (r.rbase[dy] + dz * r.lstride);
-        f32x4 f = *reinterpret_cast<const f32x4*>(row + (uint32_t)x0);
+        // read once: a streaming (non-temporal) load
+        f32x4 f = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(row + (uint32_t)x0));
         float* o = val + 16 * dz + 4 * dy;
         o[0] = f.x;
         o[1] = f.y;
@@ -392,7 +393,7 @@ __device__ __forceinline__ void gstore64(uint64_t* p, uint64_t v) {
   if (COH)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   else
-    *p = v;
+    __builtin_nontemporal_store(v, p);  // written once: streaming
 }
 template <bool COH>
 __device__ __forceinline__ uint64_t gload64(const uint64_t* p) {
