@@ -101,6 +101,7 @@ struct ServeCtl {        // host-coherent control block
 struct ServeDevCtl {     // device-memory mirror written by the dispatcher
   uint64_t published;    // requests copied into ring_dev
   uint64_t stop;         // set once the host asked the loop to stop
+  uint64_t oldest;       // a copy of the host's hint; it may lag, never lead
 };
 
 struct ServeDev {        // arguments of the device loop

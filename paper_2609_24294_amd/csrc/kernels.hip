@@ -988,6 +988,11 @@ static_assert(kDescWords <= 64, "one descriptor word per lane");
 __device__ __forceinline__ void serve_dispatch(const ServeDev d, int lane, uint64_t t_start) {
   uint64_t seen = dev_load(&d.dctl->published);
   uint64_t t_work = t_start;
+  // the claimers start their walk from the device copy of the host's hint
+  // (one read of host memory here, not one per claimer)
+  if (lane == 0)
+    __hip_atomic_store(&d.dctl->oldest, sys_load(&d.ctl->oldest), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
     const uint64_t now = __builtin_amdgcn_s_memrealtime();
     if (now - t_start > d.max_ticks) break;
@@ -1027,8 +1032,11 @@ __device__ __forceinline__ void serve_dispatch(const ServeDev d, int lane, uint6
         }
         wait_memory();  // complete before seq is written / before publishing
       }
-      if (lane == 0)
+      if (lane == 0) {
         __hip_atomic_store(&d.dctl->published, hpub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&d.dctl->oldest, sys_load(&d.ctl->oldest), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
       seen = hpub;
       t_work = now;
       continue;
@@ -1184,8 +1192,14 @@ void k_serve(ServeDev d) {
   }
   uint64_t* wlds = lds + (size_t)wave * 64 * lds_stride(32);
   ServeRun* run = reinterpret_cast<ServeRun*>(lds + (size_t)kServeWaves * 64 * lds_stride(32));
+  // the claimer's walk state (only the first wavefront uses it).  It starts
+  // from the device copy of the host's oldest-request hint: a launch that
+  // began with one read of host memory per wavefront (thousands of reads of
+  // one word over PCIe) took 70-120 us to start serving.  The copy may be the
+  // previous launch's until the dispatcher refreshes it; a lagging start only
+  // walks requests that are already done.
   ServeCursor c;
-  c.cursor = sys_load(&d.ctl->oldest);
+  c.cursor = wave == 0 ? dev_load(&d.dctl->oldest) : 0;
   c.pub = 0;
   c.t_work = t_start;
   c.qtag = 0;

@@ -304,7 +304,7 @@ int zfpx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t workg
     return ZFPX_ENOMEM;
   }
   {
-    ServeDevCtl z{0, 0};
+    ServeDevCtl z{0, 0, 0};
     std::vector<ServeDesc> blank(max_slots);
     memset(blank.data(), 0xff, sizeof(ServeDesc) * max_slots);
     if (hipMemcpy(sv->dctl, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess ||
