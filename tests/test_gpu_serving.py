@@ -218,6 +218,34 @@ def test_server_idle_setting(zfpx_lib):
     assert launches[50000] == 1
 
 
+def test_server_relaunch_races(zfpx_lib):
+    """A 200 us idle spell and arrivals 100-400 us apart: the loop leaves and is
+    launched again many times, requests often arriving while it is leaving.
+    Every request completes with the oracle's output."""
+    rng = np.random.default_rng(44)
+    pool = torch.from_numpy(W.serving_pool(nx_max=512)).to(DEV)
+    views = [pool[:, :, :nx] for nx in (64, 128, 256)]
+    refs = [_oracle_ref(0, 16, v) for v in views]
+    n = 150
+    which = rng.integers(0, len(views), n)
+    outs = [torch.empty_like(refs[k]) for k in which]
+    torch.cuda.synchronize()
+    reqs = [zfpx_lib.make_request(0, 16, views[k], o) for k, o in zip(which, outs)]
+    arrival = np.cumsum(rng.uniform(100e-6, 400e-6, n))
+    sv = zfpx_lib.Server(64 << 30, max_slots=16)
+    try:
+        sv.set_idle_us(200)
+        lat = sv.replay(reqs, arrival, timeout_s=60.0)
+        launches = sv.stats()["loop_launches"]
+    finally:
+        sv.close()
+    torch.cuda.synchronize()
+    assert (lat > 0).all()
+    assert launches > 1
+    for k, o in zip(which, outs):
+        assert _same(o, refs[k])
+
+
 def test_replay_forms_agree(zfpx_lib):
     rng = np.random.default_rng(42)
     pool = torch.from_numpy(W.serving_pool(nx_max=4096)).to(DEV)
