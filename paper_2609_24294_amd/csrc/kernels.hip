@@ -686,10 +686,6 @@ __global__ __launch_bounds__(256) void k_encode_var(Geo geo, const float* __rest
   }
 }
 
-// Tile offsets: exclusive prefix sums of the tile counts, and the total.  One
-// workgroup walks the counts in chunks of 8192: a coalesced load into LDS,
-// each thread sums 8 consecutive counts, a workgroup scan of the thread sums
-// (wavefront scans, then the 16 wavefront totals), and 8 offsets per thread.
 // Tile offsets = exclusive prefix sum of the tile counts, in three launches
 // over chunks of kScanChunk counts (8 per thread of a 1024-thread group):
 // (1) each chunk's sum, parked in tile_off at the chunk's first position;
