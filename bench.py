@@ -927,6 +927,21 @@ def serving_report(torch, zfpx, W, count, workgroups=0):
                                        "gbs_fp32": round(nbytes.sum() / span_p / 1e9, 1)}
         out["points"].append(point)
         torch.cuda.empty_cache()
+    # requests 5 ms apart, past the loop's 2 ms idle spell: each one finds the
+    # loop gone and pays for a new launch (the plain form beside it)
+    log("serving: cold starts (requests 5 ms apart)")
+    cold = [q for q in base[:400] if q.nx <= 1024][:20]
+    reqs, _, _ = build(cold)
+    arrival = np.arange(len(reqs)) * 5e-3
+    sv = zfpx.Server(64 << 30, max_slots=1024, workgroups=workgroups)
+    try:
+        lc = sv.replay(reqs, arrival, timeout_s=60.0)
+        launches = sv.stats()["loop_launches"]
+    finally:
+        sv.close()
+    lp = zfpx.zfpx_plain_replay(reqs, arrival, timeout_s=60.0)
+    out["cold_start"] = {"requests": len(reqs), "gap_ms": 5.0, "loop_launches": launches,
+                         "server_p50_us": pct(lc, 50), "per_request_launch_p50_us": pct(lp, 50)}
     torch.cuda.synchronize()
     return out
 
