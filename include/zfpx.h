@@ -406,7 +406,7 @@ int zfpx_graph_destroy(zfpx_graph* graph);
  *                        no request was published (100 us .. 10 s, default
  *                        2000); taken at the loop's next launch.  A request
  *                        that finds the loop gone pays for a new launch
- *                        (about 20 us more on MI355X), while a running loop
+ *                        (about 15 us more on MI355X), while a running loop
  *                        holds most of every compute unit's LDS.
  *   zfpx_server_progress / _poll : collect completions and admit more;
  *                        poll reports done and the latency (seconds from

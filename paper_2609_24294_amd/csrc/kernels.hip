@@ -1085,8 +1085,14 @@ __device__ __forceinline__ bool serve_find_run(const ServeDev& d, int lane, uint
         // Idle workgroups poll the published counter about every 14 us: many
         // pollers of one word every microsecond slow every coherent access of
         // the loop, and with hundreds of pollers at random phases some wake
-        // within a microsecond.
-        for (int i = 0; i < 4; i++) __builtin_amdgcn_s_sleep(127);
+        // within a microsecond.  Right after a launch, which happens because
+        // requests are waiting, all of them are in phase and nothing runs yet:
+        // for the first 1/40 of the idle spell they poll every 0.5 us.
+        if (now - t_start < d.idle_ticks / 40) {
+          __builtin_amdgcn_s_sleep(16);
+        } else {
+          for (int i = 0; i < 4; i++) __builtin_amdgcn_s_sleep(127);
+        }
         continue;
       }
     }
