@@ -992,13 +992,15 @@ __device__ __forceinline__ void serve_dispatch(const ServeDev d, int lane, uint6
   for (;;) {
     const uint64_t now = __builtin_amdgcn_s_memrealtime();
     if (now - t_start > d.max_ticks) break;
-    if (sys_load32(&d.ctl->stop)) {
+    // both host words read in one round trip over PCIe
+    const uint32_t stop = sys_load32(&d.ctl->stop);
+    const uint64_t hpub = sys_load(&d.ctl->published);
+    if (stop) {
       if (lane == 0)
         __hip_atomic_store(&d.dctl->stop, uint64_t(1), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       break;
     }
-    const uint64_t hpub = sys_load(&d.ctl->published);
     if (hpub > seen) {
       // A slot is rewritten once its previous request has completed, but a
       // worker that claimed past the end of that request may still be reading
