@@ -864,7 +864,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   wave_sync_lds();
   if (lane < nact) {
     float val[64];
-    decode_block<CAP>(slice, val, cap, maxprec, minexp);
+    decode_block<CAP, true>(slice, val, cap, maxprec, minexp);
     BlockView v;
     geo.locate_tile(b0, lane, nact, v);
     scatter<VEC4>(dst, v, val);
