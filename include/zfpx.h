@@ -335,7 +335,8 @@ int zfpx_plan_var_chunk_offsets(const zfpx_plan* plan, const uint8_t* d_nd,
  * zfpx_plan_set_config stores it in the plan for that op and rate (rate 0 =
  * every rate without an entry of its own); it is then used by every launch
  * on that plan.  Returns EINVAL for an unsupported configuration.  Without
- * an entry a launch uses 128 threads and one tile per wavefront.
+ * an entry a launch uses one tile per wavefront and 128 threads, or 64 for
+ * launches of more than 2^16 tiles.
  */
 int zfpx_plan_set_config(zfpx_plan* plan, int op, int rate, int wg_threads, int grid_wgs);
 int zfpx_plan_get_config(const zfpx_plan* plan, int op, int rate, int* wg_threads,

@@ -26,11 +26,15 @@ bool rate_ok(int rate) { return rate >= 1 && rate <= 32; }
 int64_t ceil4(int64_t n) { return (n + 3) / 4; }
 bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 
-// One tile per wavefront, two wavefronts per workgroup (timed on the z->lambda
-// share with encode and decode alternating: 64 threads lose 5% and 256 match).
-LaunchCfg default_cfg(int) {
+// One tile per wavefront.  Two wavefronts per workgroup for launches up to
+// 2^16 tiles (timed on the z->lambda share, 14,105 tiles, encode and decode
+// alternating: 64 threads lose 5% and 256 match), one above (on the 9.47 GB
+// buffer, 591,560 tiles, 64 threads are 1-2% faster than 128 at rates 8 and
+// 16, both ops, and 256 slower).
+constexpr int64_t kManyTilesBlocks = int64_t(64) << 16;
+LaunchCfg default_cfg(int, int64_t nblocks) {
   LaunchCfg c;
-  c.wg = 128;
+  c.wg = nblocks > kManyTilesBlocks ? 64 : 128;
   c.grid = 0;
   return c;
 }
@@ -61,7 +65,7 @@ struct zfpx_plan {
     if (it != cfg.end()) return it->second;
     it = cfg.find({op, 0});
     if (it != cfg.end() && lds_bytes(it->second.wg, rate) <= device_max_lds()) return it->second;
-    return default_cfg(op);
+    return default_cfg(op, nblocks);
   }
 };
 
@@ -125,7 +129,8 @@ int zfpx_encode_fixed_rate(const float* d_in, int64_t nx, int64_t ny, int64_t nz
   if (!d_in || !d_out || !aligned(d_out, 8)) return ZFPX_EINVAL;
   if ((int64_t)out_bytes < nb * 8 * rate) return ZFPX_ENOSPC;
   hipError_t e = launch_regular_encode(g, regular_vec4(d_in, sx, sy, sz), d_in, (uint64_t*)d_out,
-                                       rate, (int32_t)nb, default_cfg(kOpEncode), (hipStream_t)stream);
+                                       rate, (int32_t)nb, default_cfg(kOpEncode, nb),
+                                       (hipStream_t)stream);
   return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
 }
 
@@ -140,7 +145,7 @@ int zfpx_decode_fixed_rate(const void* d_in, size_t in_bytes, int64_t nx, int64_
   if (!d_in || !d_out || !aligned(d_in, 8)) return ZFPX_EINVAL;
   if ((int64_t)in_bytes < nb * 8 * rate) return ZFPX_ENOSPC;
   hipError_t e = launch_regular_decode(g, regular_vec4(d_out, sx, sy, sz), (const uint64_t*)d_in,
-                                       d_out, rate, (int32_t)nb, default_cfg(kOpDecode),
+                                       d_out, rate, (int32_t)nb, default_cfg(kOpDecode, nb),
                                        (hipStream_t)stream);
   return e == hipSuccess ? ZFPX_OK : ZFPX_EHIP;
 }
@@ -600,7 +605,7 @@ int zfpx_autotune(zfpx_plan* p, int op, int rate, const float* d_src, int64_t sr
   }
   auto saved = p->cfg;
   double best = 1e300;
-  LaunchCfg best_c = default_cfg(op);
+  LaunchCfg best_c = default_cfg(op, p->nblocks);
   int st = ZFPX_OK;
   for (const LaunchCfg& c : cands) {
     p->cfg[{op, rate}] = c;
