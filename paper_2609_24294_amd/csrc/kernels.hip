@@ -1270,23 +1270,32 @@ void k_serve(ServeDev d) {
 }
 
 // float16 comparator; unaligned buffers take one value per thread.
-// Truncate: groups of 8 values (two 16-byte loads, one 16-byte store), one
-// group per thread on a grid that covers the buffer (the loop only runs more
-// than once beyond kElementwiseMaxBlocks workgroups): many short-lived
-// wavefronts keep more loads in flight than a capped grid whose threads walk
-// several groups.
-__global__ __launch_bounds__(256) void k_f16_truncate_v8(const float4* __restrict__ in,
-                                                         size_t n8, uint4* __restrict__ out) {
-  const size_t T = (size_t)gridDim.x * blockDim.x;
+// Truncate: a wavefront converts 128 consecutive groups of 4 values; lane l
+// takes groups l and l + 64, so each 16-byte load reads 1 KB and each 8-byte
+// store writes 512 B contiguously.  Both loads are issued (clamped in range)
+// before either conversion, and loads and stores carry the non-temporal hint
+// (every byte is touched once): on a 9.47 GB buffer this runs at 80% of the
+// HBM peak against 72-74% with ordinary accesses.  The grid covers the buffer
+// (the loop only runs more than once beyond kElementwiseMaxBlocks
+// workgroups).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void k_f16_truncate_w2(const f32x4* __restrict__ in, size_t n4,
+                                                         u32x2* __restrict__ out) {
   auto h = [](float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f); };
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8; i += T) {
-    const float4 a = in[2 * i], b = in[2 * i + 1];
-    uint4 r;
-    r.x = h(a.x) | (h(a.y) << 16);
-    r.y = h(a.z) | (h(a.w) << 16);
-    r.z = h(b.x) | (h(b.y) << 16);
-    r.w = h(b.z) | (h(b.w) << 16);
-    out[i] = r;
+  const int lane = threadIdx.x & 63;
+  const size_t nw = (n4 + 127) / 128;
+  const size_t wstep = (size_t)gridDim.x * (blockDim.x / 64);
+  for (size_t w = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); w < nw;
+       w += wstep) {
+    const size_t i0 = w * 128 + lane, i1 = i0 + 64;
+    const f32x4 a = __builtin_nontemporal_load(in + (i0 < n4 ? i0 : n4 - 1));
+    const f32x4 b = __builtin_nontemporal_load(in + (i1 < n4 ? i1 : n4 - 1));
+    if (i0 < n4)
+      __builtin_nontemporal_store(u32x2{h(a.x) | (h(a.y) << 16), h(a.z) | (h(a.w) << 16)},
+                                  out + i0);
+    if (i1 < n4)
+      __builtin_nontemporal_store(u32x2{h(b.x) | (h(b.y) << 16), h(b.z) | (h(b.w) << 16)},
+                                  out + i1);
   }
 }
 
@@ -1298,14 +1307,15 @@ __global__ __launch_bounds__(256) void k_f16_truncate_s(const float* __restrict_
 }
 
 // Restore: groups of 4 values (one 8-byte load, one 16-byte store), one
-// group per thread on a covering grid, as truncate.
-__global__ __launch_bounds__(256) void k_f16_restore_v4(const uint2* __restrict__ in, size_t n4,
-                                                        float4* __restrict__ out) {
+// group per thread on a covering grid, with non-temporal loads and stores as
+// in truncate (81% of the HBM peak on a 9.47 GB output against 78%).
+__global__ __launch_bounds__(256) void k_f16_restore_v4(const u32x2* __restrict__ in, size_t n4,
+                                                        f32x4* __restrict__ out) {
   const size_t T = (size_t)gridDim.x * blockDim.x;
   auto f = [](uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)w); };
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += T) {
-    const uint2 r = in[i];
-    out[i] = make_float4(f(r.x), f(r.x >> 16), f(r.y), f(r.y >> 16));
+    const u32x2 r = __builtin_nontemporal_load(in + i);
+    __builtin_nontemporal_store(f32x4{f(r.x), f(r.x >> 16), f(r.y), f(r.y >> 16)}, out + i);
   }
 }
 
@@ -1473,11 +1483,11 @@ hipError_t launch_serve(const ServeDev& d, int workgroups, hipStream_t s) {
 hipError_t launch_f16_truncate(const float* in, size_t n, uint16_t* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
   size_t done = 0;
-  if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0 && n >= 8) {
-    size_t n8 = n / 8;
-    hipLaunchKernelGGL(k_f16_truncate_v8, dim3(covering_grid(n8)), dim3(256), 0, s,
-                       reinterpret_cast<const float4*>(in), n8, reinterpret_cast<uint4*>(out));
-    done = n8 * 8;
+  if (((uintptr_t)in & 15) == 0 && ((uintptr_t)out & 7) == 0 && n >= 4) {
+    size_t n4 = n / 4;
+    hipLaunchKernelGGL(k_f16_truncate_w2, dim3(covering_grid((n4 + 1) / 2)), dim3(256), 0, s,
+                       reinterpret_cast<const f32x4*>(in), n4, reinterpret_cast<u32x2*>(out));
+    done = n4 * 4;
   }
   if (done < n)
     hipLaunchKernelGGL(k_f16_truncate_s, dim3(elementwise_grid(n - done)), dim3(256), 0, s,
@@ -1491,7 +1501,7 @@ hipError_t launch_f16_restore(const uint16_t* in, size_t n, float* out, hipStrea
   if (((uintptr_t)in & 7) == 0 && ((uintptr_t)out & 15) == 0 && n >= 4) {
     size_t n4 = n / 4;
     hipLaunchKernelGGL(k_f16_restore_v4, dim3(covering_grid(n4)), dim3(256), 0, s,
-                       reinterpret_cast<const uint2*>(in), n4, reinterpret_cast<float4*>(out));
+                       reinterpret_cast<const u32x2*>(in), n4, reinterpret_cast<f32x4*>(out));
     done = n4 * 4;
   }
   if (done < n)
